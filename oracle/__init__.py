@@ -1,0 +1,267 @@
+"""CPU oracle for the Disentangled 4D Gaussian Splatting render path.
+
+TEST INFRASTRUCTURE ONLY.  Imported by the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark -- never by the product package.  It wraps
+liboracle.so (plain C, built from d4dgs_oracle.c by build()) through ctypes.
+
+Functions follow the paper's pipeline (Alg. 1 and Sec. 3.2):
+    project(scene, cam, t, prec)   camera stage + time stage, prec "f32" or "f64"
+    bin(proj, cam)                 16x16 tile lists ordered by (tile, depth, index)
+    blend(proj, bins, cam, bg)     Eq. 4 front to back, per pixel (FP64)
+    blend_bruteforce(...)          the same blend, per-pixel lists built by brute force
+    blend_bwd(...)                 exact adjoint of the blend (stored forward values)
+    project_bwd(...)               projection adjoint by the complex-step method
+    render(scene, cam, t, bg)      project(f32) -> bin -> blend
+    render_grad(...)               gradients of sum(dL_dimg * image) w.r.t. parameters
+
+Precision: everything that decides an integer (culls, rectangles, depth keys) runs
+in FP32 in the fixed operation order of the FP contract; blending and gradients run
+in FP64 on the FP32 splat record.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "d4dgs_oracle.c")
+
+PARAM_BLOCKS = (("mean", 3), ("scale", 3), ("quat", 4), ("opacity", 1), ("t_mean", 1),
+                ("t_scale", 1), ("velocity", 3))
+
+
+def build(force=True):
+    """Compile liboracle.so with gcc (no fast-math, no FMA contraction, OpenMP)."""
+    if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= max(
+            os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "oracle_body.inc"))):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-shared", "-fPIC", "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Scene(C.Structure):
+    _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32)] + [
+        (k, C.POINTER(C.c_double)) for k in
+        ("mean", "scale", "quat", "opacity", "t_mean", "t_scale", "velocity", "sh")]
+
+
+class _Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("tan_fovx", C.c_float), ("tan_fovy", C.c_float),
+                ("znear", C.c_float), ("R", C.c_float * 9), ("T", C.c_float * 3),
+                ("campos", C.c_float * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        L.oc_version.restype = C.c_int
+        for suf in ("f32", "f64"):
+            f = getattr(L, "oc_project_" + suf)
+            f.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 13
+            f.restype = None
+        L.oc_bin.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, P]
+        L.oc_bin.restype = C.c_int64
+        L.oc_blend.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 12
+        L.oc_blend.restype = C.c_int64
+        L.oc_blend_bruteforce.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 12
+        L.oc_blend_bruteforce.restype = None
+        L.oc_blend_bwd.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 13
+        L.oc_blend_bwd.restype = None
+        L.oc_project_bwd.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 6
+        L.oc_project_bwd.restype = None
+        L.oc_sh_basis.argtypes = [C.c_int, C.c_int, P, P]
+        L.oc_sh_basis.restype = None
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _scene_struct(scene_arrays, n, deg):
+    """scene_arrays: dict of arrays (any float dtype) -> (struct, keepalive list)."""
+    keep = []
+    s = _Scene()
+    s.n = n
+    s.sh_degree = deg
+    for k in ("mean", "scale", "quat", "opacity", "t_mean", "t_scale", "velocity", "sh"):
+        a = np.ascontiguousarray(scene_arrays[k], dtype=np.float64).reshape(-1)
+        keep.append(a)
+        setattr(s, k, a.ctypes.data_as(C.POINTER(C.c_double)))
+    return s, keep
+
+
+def _cam_struct(cam):
+    c = _Camera()
+    c.width, c.height = cam.width, cam.height
+    for k in ("fx", "fy", "cx", "cy", "tan_fovx", "tan_fovy", "znear"):
+        setattr(c, k, float(getattr(cam, k)))
+    for i in range(9):
+        c.R[i] = float(cam.R[i])
+    for i in range(3):
+        c.T[i] = float(cam.T[i])
+        c.campos[i] = float(cam.campos[i])
+    return c
+
+
+def scene_dict(scene):
+    return {k: getattr(scene, k) for k in ("mean", "scale", "quat", "opacity", "t_mean", "t_scale",
+                                           "velocity", "sh")}
+
+
+def project(scene, cam, t, prec="f32", arrays=None):
+    """Camera stage + time stage for every Gaussian.  `arrays` overrides the
+    parameters (e.g. float64 perturbed copies for finite differences)."""
+    n, deg = scene.n, scene.sh_degree
+    arr = scene_dict(scene) if arrays is None else arrays
+    s, keep = _scene_struct(arr, n, deg)
+    c = _cam_struct(cam)
+    dt = np.float32 if prec == "f32" else np.float64
+    out = {k: np.zeros((d, n), dt) for k, d in
+           (("p", 3), ("u", 3), ("covc", 6), ("m0", 2), ("md", 2), ("rgb", 3), ("m", 2), ("conic", 3))}
+    out["amax"] = np.zeros(n, dt)
+    out["w"] = np.zeros(n, dt)
+    out["depth"] = np.zeros(n, np.float32)
+    out["rect"] = np.zeros((4, n), np.int32)
+    out["count"] = np.zeros(n, np.int32)
+    f = getattr(lib(), "oc_project_" + prec)
+    f(C.byref(s), C.byref(c), float(t), *[_p(out[k]) for k in
+      ("p", "u", "covc", "m0", "md", "rgb", "m", "conic", "amax", "w", "depth", "rect", "count")])
+    del keep
+    out["n"] = n
+    return out
+
+
+def bin(proj, cam):
+    n = proj["n"]
+    count = np.ascontiguousarray(proj["count"], np.int32)
+    I = int(count.astype(np.int64).sum())
+    keys = np.zeros(max(I, 1), np.uint64)
+    vals = np.zeros(max(I, 1), np.uint32)
+    tiles = cam.tiles
+    ranges = np.zeros(2 * tiles, np.uint32)
+    got = lib().oc_bin(n, cam.width, cam.height, _p(np.ascontiguousarray(proj["rect"], np.int32)),
+                       _p(count), _p(np.ascontiguousarray(proj["depth"], np.float32)),
+                       _p(keys), _p(vals), _p(ranges))
+    assert got == I
+    return {"keys": keys[:I], "values": vals[:I], "ranges": ranges.reshape(tiles, 2), "I": I}
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def blend(proj, bins, cam, bg=(0.0, 0.0, 0.0)):
+    n, W, H = proj["n"], cam.width, cam.height
+    img = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    nc = np.zeros((H, W), np.int32)
+    fl = np.zeros((H, W), np.int32)
+    dh = np.zeros((H, W), np.uint64)
+    vals = bins["values"] if bins["I"] > 0 else np.zeros(1, np.uint32)
+    bgv = _f64(bg)
+    ne = lib().oc_blend(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])), _p(_f64(proj["amax"])),
+                        _p(_f64(proj["rgb"])), _p(np.ascontiguousarray(vals)),
+                        _p(np.ascontiguousarray(bins["ranges"], np.uint32)), _p(bgv), _p(img), _p(T),
+                        _p(nc), _p(fl), _p(dh))
+    return {"img": img, "final_T": T, "n_contrib": nc, "flags": fl, "n_eval": int(ne), "dhash": dh}
+
+
+def blend_bruteforce(proj, cam, bg=(0.0, 0.0, 0.0)):
+    n, W, H = proj["n"], cam.width, cam.height
+    img = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    nc = np.zeros((H, W), np.int32)
+    fl = np.zeros((H, W), np.int32)
+    lib().oc_blend_bruteforce(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])),
+                              _p(_f64(proj["amax"])), _p(_f64(proj["rgb"])),
+                              _p(np.ascontiguousarray(proj["rect"], np.int32)),
+                              _p(np.ascontiguousarray(proj["count"], np.int32)),
+                              _p(np.ascontiguousarray(proj["depth"], np.float32)), _p(_f64(bg)),
+                              _p(img), _p(T), _p(nc), _p(fl))
+    return {"img": img, "final_T": T, "n_contrib": nc, "flags": fl}
+
+
+def blend_bwd(proj, bins, cam, dL_dimg, bg=(0.0, 0.0, 0.0)):
+    n, W, H = proj["n"], cam.width, cam.height
+    g = {"m": np.zeros((2, n)), "conic": np.zeros((3, n)), "amax": np.zeros(n), "rgb": np.zeros((3, n))}
+    err = np.zeros(1)
+    vals = bins["values"] if bins["I"] > 0 else np.zeros(1, np.uint32)
+    lib().oc_blend_bwd(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])), _p(_f64(proj["amax"])),
+                       _p(_f64(proj["rgb"])), _p(np.ascontiguousarray(vals)),
+                       _p(np.ascontiguousarray(bins["ranges"], np.uint32)), _p(_f64(bg)),
+                       _p(_f64(dL_dimg)), _p(g["m"]), _p(g["conic"]), _p(g["amax"]), _p(g["rgb"]), _p(err))
+    g["replay_rel_err"] = float(err[0])
+    return g
+
+
+def project_bwd(scene, cam, t, active, gsplat, arrays=None):
+    """Parameter gradients from splat-level gradients, by complex step.
+    Returns a dict in the scene's planar layout."""
+    n, deg = scene.n, scene.sh_degree
+    K = (deg + 1) ** 2
+    P = 16 + 3 * K
+    arr = scene_dict(scene) if arrays is None else arrays
+    s, keep = _scene_struct(arr, n, deg)
+    c = _cam_struct(cam)
+    out = np.zeros((P, n))
+    lib().oc_project_bwd(C.byref(s), C.byref(c), float(t), _p(np.ascontiguousarray(active, np.int32)),
+                         _p(_f64(gsplat["m"])), _p(_f64(gsplat["conic"])), _p(_f64(gsplat["amax"])),
+                         _p(_f64(gsplat["rgb"])), _p(out))
+    del keep
+    return unpack_params(out, K)
+
+
+def unpack_params(flat, K):
+    res, j = {}, 0
+    for name, d in PARAM_BLOCKS:
+        res[name] = flat[j:j + d] if d > 1 else flat[j]
+        j += d
+    res["sh"] = flat[j:j + 3 * K].reshape(K, 3, -1)
+    return res
+
+
+def render(scene, cam, t, bg=(0.0, 0.0, 0.0), prec="f32", arrays=None):
+    """project -> bin -> blend.  Returns (projection, bins, blend result)."""
+    proj = project(scene, cam, t, prec, arrays)
+    bins = bin(proj, cam)
+    res = blend(proj, bins, cam, bg)
+    return proj, bins, res
+
+
+def render_grad(scene, cam, t, dL_dimg, bg=(0.0, 0.0, 0.0), prec="f32", arrays=None, mask=None):
+    """Gradient of sum(dL_dimg * image) with respect to every parameter.  `mask`
+    (H, W) zeroes the upstream gradient at excluded pixels."""
+    proj, bins, res = render(scene, cam, t, bg, prec, arrays)
+    gin = np.array(dL_dimg, dtype=np.float64)
+    if mask is not None:
+        gin = gin * (~mask)[None]
+    gs = blend_bwd(proj, bins, cam, gin, bg)
+    active = (proj["count"] > 0).astype(np.int32)
+    gp = project_bwd(scene, cam, t, active, gs, arrays)
+    return gp, gs, (proj, bins, res)
+
+
+def sh_basis(deg, dirs):
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    K = (deg + 1) ** 2
+    Y = np.zeros((dirs.shape[0], K))
+    lib().oc_sh_basis(deg, dirs.shape[0], _p(dirs), _p(Y))
+    return Y
