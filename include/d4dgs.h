@@ -1,0 +1,263 @@
+/*
+ * d4dgs.h -- C ABI of the MI355X (gfx950) render path for Disentangled 4D Gaussian
+ * Splatting (Feng et al., "Disentangled 4D Gaussian Splatting: Rendering
+ * High-Resolution Dynamic World at 343 FPS").
+ *
+ * A frame at camera C and time t is rendered in four stages, each enqueued
+ * asynchronously on the caller's HIP stream:
+ *
+ *   d4dgs_project     camera stage (once per camera) + time stage (per frame):
+ *                     Alg. 1; Eq. 9-15 (projection first, temporal processing
+ *                     deferred: temporal opacity falloff and screen-space motion
+ *                     are applied after the spatial projection).
+ *   d4dgs_bin_sort    tile binning of the projected splats and a depth-keyed LSD
+ *                     radix sort into per-tile front-to-back lists (the tiled
+ *                     rasteriser the paper adopts from 3D Gaussian Splatting, Sec. 3.2.2).
+ *   d4dgs_render_fwd  per-tile front-to-back alpha blending, Eq. 4.
+ *   d4dgs_render_bwd  adjoint of the three stages above (the differentiable
+ *                     pipeline of Fig. 3): replays each pixel's transmittance in
+ *                     reverse from its final value and returns gradients for every
+ *                     per-Gaussian parameter, including mu_t, s_t and the velocity.
+ *   d4dgs_serve_*     a continuous-batching render server over one resident scene.
+ *
+ * Conventions
+ *  - Every pointer marked (device) is device memory owned by the caller; the library
+ *    never frees it and never keeps it beyond the call (the server is the exception:
+ *    it keeps the scene pointers until d4dgs_serve_destroy).
+ *  - Compute entry points only enqueue work on `stream` (a hipStream_t; NULL is the
+ *    legacy default stream) and return without waiting, unless documented otherwise.
+ *  - No entry point allocates device memory on the render path: scratch comes from
+ *    caller workspaces (d4dgs_workspace_size) or from the server's arena.
+ *  - Errors are returned as d4dgs_status; nothing is thrown across the ABI.  A text
+ *    description of the last error on the calling thread is in d4dgs_last_error().
+ *  - Layouts are planar (structure of arrays) unless stated: a [3][n] array holds
+ *    all x, then all y, then all z.
+ */
+#ifndef D4DGS_H
+#define D4DGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define D4DGS_ABI_VERSION 1
+#define D4DGS_TILE 16           /* tile edge in pixels */
+#define D4DGS_CAM_REC_FLOATS 19 /* camera-stage record: p3 u3 covc6 m0_2 md2 rgb3 */
+#define D4DGS_REC_FLOATS 12     /* splat record, 3 x float4 per Gaussian */
+#define D4DGS_GRAD_FLOATS 12    /* per-instance splat gradient, 3 x float4 */
+#define D4DGS_MAX_SH_DEGREE 3
+
+typedef enum {
+    D4DGS_OK = 0,
+    D4DGS_ERR_INVALID_ARG = 1,   /* a pointer, size or camera field is unusable */
+    D4DGS_ERR_OUT_OF_MEMORY = 2, /* a caller buffer or the server arena is too small */
+    D4DGS_ERR_CAPACITY = 3,      /* more tile instances than the instance capacity */
+    D4DGS_ERR_HIP = 4,           /* the HIP runtime reported an error */
+    D4DGS_ERR_BUSY = 5,          /* the server queue is full */
+    D4DGS_ERR_NOT_FOUND = 6,     /* unknown ticket */
+    D4DGS_ERR_TIMEOUT = 7        /* a wait ran out of time */
+} d4dgs_status;
+
+typedef void *d4dgs_stream; /* hipStream_t */
+
+/* Disentangled 4D Gaussians (Eq. 8: s_4D, mu_4D, q, V_3D) plus opacity and colour.
+ * All (device), float32, borrowed.  Activated values: scale > 0, t_scale > 0,
+ * 0 < opacity < 1.  quat is scalar first (w, x, y, z) and need not be normalised;
+ * a zero quaternion culls the Gaussian.  sh is [K][3][n], K = (sh_degree + 1)^2,
+ * real spherical harmonics with the Condon-Shortley phase, k = l*l + l + m;
+ * colour = max(0, sum_k Y_k(d) sh[k] + 0.5), d the unit direction from the
+ * camera centre to the (static) spatial mean. */
+typedef struct {
+    int32_t n;
+    int32_t sh_degree; /* 0..3 */
+    const float *mean;     /* [3][n] mu_x, mu_y, mu_z */
+    const float *scale;    /* [3][n] s_x, s_y, s_z */
+    const float *quat;     /* [4][n] */
+    const float *opacity;  /* [n] */
+    const float *t_mean;   /* [n] mu_t */
+    const float *t_scale;  /* [n] s_t */
+    const float *velocity; /* [3][n] velocity of the mean, d mu / dt */
+    const float *sh;       /* [K][3][n] */
+} d4dgs_scene;
+
+/* Pinhole camera (host struct).  R is world-to-camera, row major; the camera looks
+ * along +z with x right and y down; pixel (px, py) is sampled at (px + 0.5, py + 0.5).
+ * tan_fovx = width / (2 fx), tan_fovy = height / (2 fy): passed rather than derived
+ * so that every implementation uses the same bits.  znear > 0. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float tan_fovx, tan_fovy;
+    float znear;
+    float R[9];
+    float T[3];
+    float campos[3]; /* camera centre in world space (= -R^T T) */
+} d4dgs_camera;
+
+/* Camera-stage cache (Alg. 1: the camera branch runs only when the camera changes).
+ * `rec` (device) holds D4DGS_CAM_REC_FLOATS * capacity floats, planar
+ * [p.xyz, u.xyz, covc(00,01,02,11,12,22), m0.xy, md.xy, rgb][capacity].  The library
+ * fills the other fields; set `valid` to 0 after changing the scene's parameters. */
+typedef struct {
+    float *rec;
+    int32_t capacity;
+    int32_t valid;
+    d4dgs_camera cam;
+    const void *scene_key;
+    int32_t scene_n, scene_sh_degree;
+    uint64_t hits, misses; /* statistics */
+} d4dgs_cam_cache;
+
+/* Per-frame splat record written by d4dgs_project (all device, capacity >= scene n).
+ *   rec    [n][12] floats (48 B per Gaussian, 16-byte aligned):
+ *          {m.x, m.y, conic.a, conic.b, conic.c, amax, r, g, b, depth,
+ *           rect0, rect1}
+ *          m = 2D mean at t in pixels, conic = inverse of the dilated 2D covariance
+ *          (a = inv[0][0], b = inv[0][1], c = inv[1][1]), amax = o * w(t), rgb the
+ *          colour, depth = camera-space z of the mean at t; rect0/rect1 are uint32 bit
+ *          patterns x0 | y0 << 16 and x1 | y1 << 16 (tiles, half open).  Only written
+ *          for Gaussians with count > 0.
+ *   count  [n] uint32 tiles touched (0 = culled).
+ *   offset [n] uint32 exclusive prefix of count (written by d4dgs_bin_sort).
+ *   partial [ceil(capacity / 256)] uint32 scratch: per-block sums of count written by
+ *          d4dgs_project and turned into block offsets by d4dgs_bin_sort. */
+typedef struct {
+    int32_t capacity;
+    float *rec;
+    uint32_t *count;
+    uint32_t *offset;
+    uint32_t *partial;
+} d4dgs_splats;
+
+/* Sorted tile lists written by d4dgs_bin_sort (all device, caller-owned).
+ *   keys    [capacity] uint64 (tile << 32) | float-bits(depth), ascending
+ *   values  [capacity] uint32 Gaussian index (ties in key by ascending index)
+ *   ranges  [2 * tiles] uint32 [start, end) of each tile's list, tile = ty * TX + tx
+ *   num_instances  one int64: total instances (may exceed capacity on overflow) */
+typedef struct {
+    int64_t capacity;
+    uint64_t *keys;
+    uint32_t *values;
+    uint32_t *ranges;
+    int64_t *num_instances;
+} d4dgs_bins;
+
+/* Parameter gradients, same planar shapes as d4dgs_scene (all device, float32).
+ * d4dgs_render_bwd ADDS into them; zero them first. */
+typedef struct {
+    float *mean, *scale, *quat, *opacity, *t_mean, *t_scale, *velocity, *sh;
+} d4dgs_grads;
+
+int32_t d4dgs_abi_version(void);
+const char *d4dgs_last_error(void);
+
+/* Bytes of scratch d4dgs_bin_sort needs for n Gaussians, a width x height image and
+ * up to max_instances tile instances.  Writes *bytes; the caller allocates them
+ * (device, 256-byte aligned). */
+d4dgs_status d4dgs_workspace_size(int32_t n, int32_t width, int32_t height, int64_t max_instances,
+                                  size_t *bytes);
+
+/* Camera stage (if `cache` is NULL or misses) and time stage at time t for all
+ * scene Gaussians: Alg. 1 camera branch and per-timestamp steps; Eq. 9-15.  Writes
+ * splats->rec (for survivors) and splats->count.  With a cache, a bitwise-equal camera
+ * on the same scene skips the camera stage.  INVALID_ARG on a bad camera or sizes. */
+d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, float t,
+                           d4dgs_cam_cache *cache, d4dgs_splats *splats, d4dgs_stream stream);
+
+/* Tile binning and depth sort of the projected splats (the 3DGS tiled rasteriser the
+ * paper uses, Sec. 3.2.2): exclusive scan of counts into splats->offset, emission of
+ * (tile, depth) keys for every tile of each splat's rectangle, stable LSD radix sort,
+ * per-tile ranges.  If the instance total exceeds bins->capacity, *d_status (device
+ * int32, may be NULL) is set to D4DGS_ERR_CAPACITY and only the first capacity
+ * instances are kept.  workspace: d4dgs_workspace_size bytes (device). */
+d4dgs_status d4dgs_bin_sort(const d4dgs_splats *splats, int32_t n, int32_t width, int32_t height,
+                            void *workspace, size_t workspace_bytes, d4dgs_bins *bins,
+                            int32_t *d_status, d4dgs_stream stream);
+
+/* As d4dgs_bin_sort, then waits for the stream and returns D4DGS_ERR_CAPACITY on
+ * overflow; *num_instances (host, may be NULL) receives the instance total. */
+d4dgs_status d4dgs_bin_sort_sync(const d4dgs_splats *splats, int32_t n, int32_t width, int32_t height,
+                                 void *workspace, size_t workspace_bytes, d4dgs_bins *bins,
+                                 int64_t *num_instances, d4dgs_stream stream);
+
+/* Front-to-back blending per tile (Eq. 4, alpha_i = o_i w_i G'_i): for each pixel,
+ * over its tile's list: skip a splat whose exponent is positive or whose alpha
+ * (= min(0.99, amax * G)) is below 1/255; stop before a splat that would bring the
+ * transmittance below 1e-4.  img (device) [3][height][width] = C + T * bg.
+ * final_T [height][width] and n_contrib [height][width] (device, uint32: list
+ * position + 1 of the last blended splat) are the replay state of the backward;
+ * pass NULL for both to render only. */
+d4dgs_status d4dgs_render_fwd(const d4dgs_splats *splats, const d4dgs_bins *bins, int32_t width,
+                              int32_t height, const float bg[3], float *img, float *final_T,
+                              uint32_t *n_contrib, d4dgs_stream stream);
+
+/* Adjoint of d4dgs_project + d4dgs_render_fwd at the same (scene, camera, t) and the
+ * same splats/bins/replay state.  dL_dimg (device) [3][height][width].  Replays each
+ * pixel's transmittance backwards from final_T (no per-splat forward state), writes
+ * one gradient per tile instance into inst_grads (device, D4DGS_GRAD_FLOATS * capacity
+ * floats; exposed for stage tests), then sums each Gaussian's instances in a fixed
+ * order and applies the chain rule through the time and camera stages.  Adds into
+ * `grads`.  Deterministic: no atomics. */
+d4dgs_status d4dgs_render_bwd(const d4dgs_scene *scene, const d4dgs_camera *cam, float t,
+                              const d4dgs_splats *splats, const d4dgs_bins *bins, const float bg[3],
+                              const float *final_T, const uint32_t *n_contrib, const float *dL_dimg,
+                              float *inst_grads, d4dgs_grads *grads, d4dgs_stream stream);
+
+/* ------------------------------------------------------------------ serving ------
+ * A server keeps one scene resident and renders requests (camera, t, resolution) as
+ * they arrive.  Requests are admitted while fewer than max_inflight are on the GPU and
+ * their scratch fits the free part of the arena (scratch_budget_bytes, reserved at
+ * creation); admitted requests are grouped into batches whose projection runs as one
+ * launch over (request x Gaussian); batches run on n_streams streams so that one
+ * batch's blending overlaps the next batch's projection.  A request's image is
+ * bitwise the same whether it is rendered alone or in a batch.  submit/poll/wait/
+ * stats are thread-safe. */
+typedef struct {
+    int32_t max_inflight;         /* requests on the GPU at once, e.g. 64 */
+    int32_t max_batch;            /* requests per batch, <= max_inflight */
+    int64_t scratch_budget_bytes; /* arena size, e.g. 8 GiB */
+    int32_t n_streams;            /* e.g. 4 */
+    float bg[3];
+    int64_t max_instances_per_pixel_x1000; /* instance capacity per request =
+                                              width * height * this / 1000 (e.g. 1000) */
+} d4dgs_serve_config;
+
+typedef struct {
+    int64_t submit_ns, admit_ns, start_ns, done_ns; /* host steady clock */
+    int64_t num_instances;
+    int32_t status;  /* d4dgs_status of the request */
+    int32_t batch_size;
+} d4dgs_req_stats;
+
+typedef struct {
+    int64_t submitted, completed, rejected, retried;
+    int64_t queued, inflight;
+    int64_t batches;
+    int64_t arena_bytes, arena_peak_bytes;
+} d4dgs_serve_stats;
+
+typedef struct d4dgs_server d4dgs_server;
+
+/* The scene must stay valid until destroy. */
+d4dgs_status d4dgs_serve_create(const d4dgs_scene *scene, const d4dgs_serve_config *cfg,
+                                d4dgs_server **out);
+/* Queue a request; never blocks.  out_img (device) [3][height][width] is written
+ * before the request is reported done.  BUSY when the queue holds 4 * max_inflight. */
+d4dgs_status d4dgs_serve_submit(d4dgs_server *s, const d4dgs_camera *cam, float t, float *out_img,
+                                uint64_t *ticket);
+/* *done = 1 once the image is complete (stats filled, the ticket is then released). */
+d4dgs_status d4dgs_serve_poll(d4dgs_server *s, uint64_t ticket, int32_t *done, d4dgs_req_stats *st);
+/* Blocks until done or timeout_ns passes (TIMEOUT); fills st and releases the ticket. */
+d4dgs_status d4dgs_serve_wait(d4dgs_server *s, uint64_t ticket, int64_t timeout_ns, d4dgs_req_stats *st);
+d4dgs_status d4dgs_serve_stats_get(d4dgs_server *s, d4dgs_serve_stats *st);
+/* Cancels queued requests (status INVALID_ARG... reported as NOT_FOUND afterwards),
+ * drains in-flight ones, frees the arena and streams. */
+d4dgs_status d4dgs_serve_destroy(d4dgs_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* D4DGS_H */

@@ -87,8 +87,15 @@ def lib():
         L.oc_project_bwd.restype = None
         L.oc_sh_basis.argtypes = [C.c_int, C.c_int, P, P]
         L.oc_sh_basis.restype = None
+        L.oc_set_threads.argtypes = [C.c_int]
+        L.oc_set_threads.restype = None
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle (0 = all processors)."""
+    lib().oc_set_threads(int(n))
 
 
 def _p(a):

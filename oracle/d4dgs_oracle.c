@@ -72,11 +72,14 @@ struct sh_tab {
 static double fact(int k) { double f = 1.0; for (int i = 2; i <= k; ++i) f *= i; return f; }
 static double binom(int a, int b) { return fact(a) / (fact(b) * fact(a - b)); }
 
-static const struct sh_tab *sh_tables(void)
+static struct sh_tab g_sh_tab;
+
+static const struct sh_tab *sh_tables(void) { return &g_sh_tab; }
+
+/* Built once when the library is loaded, before any (OpenMP) caller can read it. */
+__attribute__((constructor)) static void sh_tables_init(void)
 {
-    static struct sh_tab tb;
-    static int ready = 0;
-    if (ready) return &tb;
+    struct sh_tab tb;
     memset(&tb, 0, sizeof(tb));
     for (int l = 0; l <= 3; ++l) {
         /* Legendre: P_l(z) = 2^-l sum_k (-1)^k C(l,k) C(2l-2k,l) z^(l-2k) */
@@ -95,9 +98,11 @@ static const struct sh_tab *sh_tables(void)
             tb.norm[l][m] = (m == 0) ? sqrt(k2) : sqrt(2.0) * sqrt(k2) * ((m & 1) ? -1.0 : 1.0);
         }
     }
-    ready = 1;
-    return &tb;
+    g_sh_tab = tb;
 }
+
+/* Thread count of the OpenMP regions (0 = the OpenMP default). */
+void oc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
 
 /* ---------------- three instantiations of the body ---------------- */
 #define REAL float

@@ -1,0 +1,267 @@
+// C ABI of libd4dgs: argument checks, the camera-stage cache, workspace carving and
+// launches.  Every entry point enqueues on the caller's stream and returns.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+
+namespace d4 {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+CamK make_camk(const d4dgs_camera &c) {
+    CamK k;
+    for (int i = 0; i < 9; ++i) k.R[i] = c.R[i];
+    for (int i = 0; i < 3; ++i) {
+        k.T[i] = c.T[i];
+        k.campos[i] = c.campos[i];
+    }
+    k.fx = c.fx;
+    k.fy = c.fy;
+    k.cx = c.cx;
+    k.cy = c.cy;
+    // guard band of the Jacobian: 1.3 x the half field of view, rounded as in float
+    volatile float g = kGuard;
+    k.limx = g * c.tan_fovx;
+    k.limy = g * c.tan_fovy;
+    k.znear = c.znear;
+    k.W = c.width;
+    k.H = c.height;
+    k.TX = (c.width + kTile - 1) / kTile;
+    k.TY = (c.height + kTile - 1) / kTile;
+    return k;
+}
+
+SceneK make_scenek(const d4dgs_scene &s) {
+    SceneK k;
+    k.n = s.n;
+    k.deg = s.sh_degree;
+    k.mean = s.mean;
+    k.scale = s.scale;
+    k.quat = s.quat;
+    k.opacity = s.opacity;
+    k.t_mean = s.t_mean;
+    k.t_scale = s.t_scale;
+    k.velocity = s.velocity;
+    k.sh = s.sh;
+    return k;
+}
+
+}  // namespace d4
+
+using namespace d4;
+
+namespace {
+
+d4dgs_status fail(d4dgs_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+d4dgs_status hip_status(hipError_t e, const char *where) {
+    if (e == hipSuccess) return D4DGS_OK;
+    set_error(std::string(where) + ": " + hipGetErrorString(e));
+    return D4DGS_ERR_HIP;
+}
+
+bool finite(float x) { return std::isfinite(x); }
+
+d4dgs_status check_scene(const d4dgs_scene *s) {
+    if (!s) return fail(D4DGS_ERR_INVALID_ARG, "scene is NULL");
+    if (s->n < 0) return fail(D4DGS_ERR_INVALID_ARG, "scene n < 0");
+    if (s->sh_degree < 0 || s->sh_degree > D4DGS_MAX_SH_DEGREE)
+        return fail(D4DGS_ERR_INVALID_ARG, "sh_degree must be 0..3");
+    if (s->n > 0 && (!s->mean || !s->scale || !s->quat || !s->opacity || !s->t_mean || !s->t_scale ||
+                     !s->velocity || !s->sh))
+        return fail(D4DGS_ERR_INVALID_ARG, "scene array is NULL");
+    return D4DGS_OK;
+}
+
+d4dgs_status check_camera(const d4dgs_camera *c) {
+    if (!c) return fail(D4DGS_ERR_INVALID_ARG, "camera is NULL");
+    if (c->width <= 0 || c->height <= 0 || c->width > 65535 * kTile || c->height > 65535 * kTile)
+        return fail(D4DGS_ERR_INVALID_ARG, "camera size out of range");
+    if (!(c->fx > 0.f) || !(c->fy > 0.f) || !finite(c->fx) || !finite(c->fy) || !finite(c->cx) ||
+        !finite(c->cy))
+        return fail(D4DGS_ERR_INVALID_ARG, "camera intrinsics invalid");
+    if (!(c->tan_fovx > 0.f) || !(c->tan_fovy > 0.f) || !finite(c->tan_fovx) || !finite(c->tan_fovy))
+        return fail(D4DGS_ERR_INVALID_ARG, "camera field of view invalid");
+    if (!(c->znear > 0.f) || !finite(c->znear)) return fail(D4DGS_ERR_INVALID_ARG, "znear must be > 0");
+    for (int i = 0; i < 9; ++i)
+        if (!finite(c->R[i])) return fail(D4DGS_ERR_INVALID_ARG, "camera rotation not finite");
+    for (int i = 0; i < 3; ++i)
+        if (!finite(c->T[i]) || !finite(c->campos[i])) return fail(D4DGS_ERR_INVALID_ARG, "camera position not finite");
+    return D4DGS_OK;
+}
+
+d4dgs_status check_splats(const d4dgs_splats *sp, int n) {
+    if (!sp) return fail(D4DGS_ERR_INVALID_ARG, "splats is NULL");
+    if (sp->capacity < n) return fail(D4DGS_ERR_OUT_OF_MEMORY, "splats capacity smaller than n");
+    if (n > 0 && (!sp->rec || !sp->count || !sp->offset || !sp->partial))
+        return fail(D4DGS_ERR_INVALID_ARG, "splats array is NULL");
+    return D4DGS_OK;
+}
+
+d4dgs_status check_bins(const d4dgs_bins *b) {
+    if (!b) return fail(D4DGS_ERR_INVALID_ARG, "bins is NULL");
+    if (b->capacity < 1 || b->capacity > (int64_t)0x7fffffff)
+        return fail(D4DGS_ERR_INVALID_ARG, "bins capacity must be in [1, 2^31)");
+    if (!b->keys || !b->values || !b->ranges || !b->num_instances)
+        return fail(D4DGS_ERR_INVALID_ARG, "bins array is NULL");
+    return D4DGS_OK;
+}
+
+#define D4_TRY(x)                          \
+    do {                                   \
+        const d4dgs_status _s = (x);       \
+        if (_s != D4DGS_OK) return _s;     \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int32_t d4dgs_abi_version(void) { return D4DGS_ABI_VERSION; }
+
+const char *d4dgs_last_error(void) { return g_err.c_str(); }
+
+d4dgs_status d4dgs_workspace_size(int32_t n, int32_t width, int32_t height, int64_t max_instances, size_t *bytes) {
+    if (!bytes) return fail(D4DGS_ERR_INVALID_ARG, "bytes is NULL");
+    if (n < 0 || width <= 0 || height <= 0 || max_instances < 1 || max_instances > (int64_t)0x7fffffff)
+        return fail(D4DGS_ERR_INVALID_ARG, "workspace sizes out of range");
+    *bytes = sort_workspace_bytes(n, max_instances);
+    return D4DGS_OK;
+}
+
+d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, d4dgs_cam_cache *cache,
+                           d4dgs_splats *splats, d4dgs_stream stream) {
+    D4_TRY(check_scene(scene));
+    D4_TRY(check_camera(cam));
+    D4_TRY(check_splats(splats, scene->n));
+    if (!std::isfinite(t)) return fail(D4DGS_ERR_INVALID_ARG, "t not finite");
+    const SceneK sk = make_scenek(*scene);
+    const CamK ck = make_camk(*cam);
+    int mode = 0;
+    float *crec = nullptr;
+    int ccap = 0;
+    if (cache) {
+        if (!cache->rec || cache->capacity < scene->n)
+            return fail(D4DGS_ERR_OUT_OF_MEMORY, "camera cache capacity smaller than n");
+        crec = cache->rec;
+        ccap = cache->capacity;
+        const bool hit = cache->valid && cache->scene_key == (const void *)scene->mean && cache->scene_n == scene->n &&
+                         cache->scene_sh_degree == scene->sh_degree &&
+                         std::memcmp(&cache->cam, cam, sizeof(d4dgs_camera)) == 0;
+        if (hit) {
+            mode = 2;
+            cache->hits++;
+        } else {
+            mode = 1;
+            cache->misses++;
+        }
+    }
+    const hipError_t e = launch_project(sk, ck, t, mode, crec, ccap, (float4 *)splats->rec, splats->count,
+                                        splats->partial, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        if (cache) cache->valid = 0;
+        return hip_status(e, "d4dgs_project");
+    }
+    if (cache && mode == 1) {
+        cache->cam = *cam;
+        cache->scene_key = (const void *)scene->mean;
+        cache->scene_n = scene->n;
+        cache->scene_sh_degree = scene->sh_degree;
+        cache->valid = 1;
+    }
+    return D4DGS_OK;
+}
+
+d4dgs_status d4dgs_bin_sort(const d4dgs_splats *splats, int32_t n, int32_t width, int32_t height, void *workspace,
+                            size_t workspace_bytes, d4dgs_bins *bins, int32_t *d_status, d4dgs_stream stream) {
+    if (n < 0) return fail(D4DGS_ERR_INVALID_ARG, "n < 0");
+    D4_TRY(check_splats(splats, n));
+    D4_TRY(check_bins(bins));
+    if (width <= 0 || height <= 0 || width > 65535 * kTile || height > 65535 * kTile)
+        return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
+    if (!workspace) return fail(D4DGS_ERR_INVALID_ARG, "workspace is NULL");
+    if (workspace_bytes < sort_workspace_bytes(n, bins->capacity))
+        return fail(D4DGS_ERR_OUT_OF_MEMORY, "workspace smaller than d4dgs_workspace_size");
+    d4dgs_camera dummy;
+    std::memset(&dummy, 0, sizeof(dummy));
+    dummy.width = width;
+    dummy.height = height;
+    const CamK ck = make_camk(dummy);
+    const SortWs ws = carve_workspace(workspace, n, bins->capacity);
+    const hipError_t e = launch_bin_sort((const float4 *)splats->rec, splats->count, splats->offset, splats->partial,
+                                         n, ck, ws, bins->keys, bins->values, bins->ranges, bins->num_instances,
+                                         bins->capacity, d_status, (hipStream_t)stream);
+    return hip_status(e, "d4dgs_bin_sort");
+}
+
+d4dgs_status d4dgs_bin_sort_sync(const d4dgs_splats *splats, int32_t n, int32_t width, int32_t height,
+                                 void *workspace, size_t workspace_bytes, d4dgs_bins *bins, int64_t *num_instances,
+                                 d4dgs_stream stream) {
+    D4_TRY(d4dgs_bin_sort(splats, n, width, height, workspace, workspace_bytes, bins, nullptr, stream));
+    const SortWs ws = carve_workspace(workspace, n, bins->capacity);
+    int64_t total = 0;
+    uint32_t misc[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(&total, bins->num_instances, sizeof(total), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(misc, ws.misc, sizeof(misc), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    D4_TRY(hip_status(e, "d4dgs_bin_sort_sync"));
+    if (num_instances) *num_instances = total;
+    if (misc[1] == (uint32_t)D4DGS_ERR_CAPACITY)
+        return fail(D4DGS_ERR_CAPACITY, "tile instances (" + std::to_string(total) + ") exceed capacity (" +
+                                            std::to_string(bins->capacity) + ")");
+    return D4DGS_OK;
+}
+
+d4dgs_status d4dgs_render_fwd(const d4dgs_splats *splats, const d4dgs_bins *bins, int32_t width, int32_t height,
+                              const float bg[3], float *img, float *final_T, uint32_t *n_contrib,
+                              d4dgs_stream stream) {
+    if (!splats || !splats->rec) return fail(D4DGS_ERR_INVALID_ARG, "splats is NULL");
+    D4_TRY(check_bins(bins));
+    if (width <= 0 || height <= 0 || width > 65535 * kTile || height > 65535 * kTile)
+        return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
+    if (!bg || !img) return fail(D4DGS_ERR_INVALID_ARG, "bg or img is NULL");
+    if ((final_T == nullptr) != (n_contrib == nullptr))
+        return fail(D4DGS_ERR_INVALID_ARG, "final_T and n_contrib must both be given or both be NULL");
+    d4dgs_camera dummy;
+    std::memset(&dummy, 0, sizeof(dummy));
+    dummy.width = width;
+    dummy.height = height;
+    const CamK ck = make_camk(dummy);
+    const hipError_t e = launch_blend((const float4 *)splats->rec, bins->values, bins->ranges, ck, bg, img, final_T,
+                                      n_contrib, (hipStream_t)stream);
+    return hip_status(e, "d4dgs_render_fwd");
+}
+
+d4dgs_status d4dgs_render_bwd(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, const d4dgs_splats *splats,
+                              const d4dgs_bins *bins, const float bg[3], const float *final_T,
+                              const uint32_t *n_contrib, const float *dL_dimg, float *inst_grads, d4dgs_grads *grads,
+                              d4dgs_stream stream) {
+    D4_TRY(check_scene(scene));
+    D4_TRY(check_camera(cam));
+    D4_TRY(check_splats(splats, scene->n));
+    D4_TRY(check_bins(bins));
+    if (!bg || !final_T || !n_contrib || !dL_dimg || !inst_grads || !grads)
+        return fail(D4DGS_ERR_INVALID_ARG, "render_bwd: NULL argument");
+    if (scene->n > 0 && (!grads->mean || !grads->scale || !grads->quat || !grads->opacity || !grads->t_mean ||
+                         !grads->t_scale || !grads->velocity || !grads->sh))
+        return fail(D4DGS_ERR_INVALID_ARG, "render_bwd: gradient array is NULL");
+    const SceneK sk = make_scenek(*scene);
+    const CamK ck = make_camk(*cam);
+    hipError_t e = launch_blend_bwd((const float4 *)splats->rec, splats->offset, bins->values, bins->ranges, ck, bg,
+                                    final_T, n_contrib, dL_dimg, (float4 *)inst_grads, bins->capacity,
+                                    (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = launch_project_bwd(sk, ck, t, (const float4 *)splats->rec, splats->count, splats->offset,
+                               (const float4 *)inst_grads, bins->capacity, *grads, (hipStream_t)stream);
+    return hip_status(e, "d4dgs_render_bwd");
+}
+
+}  // extern "C"

@@ -1,0 +1,419 @@
+// Adjoint of the render path (the differentiable pipeline of Fig. 3).
+//
+// k_blend_bwd   one wavefront per 16x16 tile, four pixels per lane, walking the tile's
+//               list from the wave's last contributor back to the front.  Each pixel's
+//               transmittance is replayed backwards from its final value,
+//               T_i = T_{i+1} / (1 - alpha_i), and the suffix colour
+//               S_i = sum_{j>i} c_j alpha_j T_j + T_final bg is carried along, so
+//                 dC/dc_i     = alpha_i T_i
+//                 dC/dalpha_i = c_i T_i - S_i / (1 - alpha_i).
+//               No per-splat forward state is stored.  alpha_i is recomputed by the same
+//               instructions as the forward, so skip decisions match exactly.  The nine
+//               per-splat gradients (m, conic, amax, rgb) are summed over the wave and
+//               written to the instance's own slot: slot = offset[g] + position of the
+//               tile inside g's rectangle, i.e. the instance's pre-sort emission index.
+//               Every slot is written exactly once; no atomics.
+// k_project_bwd one thread per Gaussian: sums its contiguous slots in a fixed order
+//               (deterministic), then applies the chain rule through the time stage
+//               (alpha_max = o w, w = exp(-tau^2 / 2 s_t^2), m = m0 + tau mdot, Jacobian at
+//               the moved mean, Sigma' = J V J^T + 0.3 I, conic = Sigma'^-1) and the camera
+//               stage (V = R Sigma R^T, Sigma = (Rq S)(Rq S)^T, normalised quaternion,
+//               p = R mu + T, u = R v, spherical-harmonic colour along mu - campos).
+//               Adds into the caller's gradient arrays.
+#include "internal.hpp"
+
+namespace d4 {
+
+namespace {
+
+constexpr int kPx = 4;
+
+__device__ __forceinline__ uint32_t inst_slot(const float4 *__restrict__ rec, const uint32_t *__restrict__ offset,
+                                              uint32_t gi, int tx, int ty) {
+    const float4 r2 = rec[3 * (size_t)gi + 2];
+    const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
+    const uint32_t x0 = lo & 0xffffu, y0 = lo >> 16, x1 = hi & 0xffffu;
+    return offset[gi] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
+}
+
+__global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ rec,
+                                                     const uint32_t *__restrict__ offset,
+                                                     const uint32_t *__restrict__ vals,
+                                                     const uint32_t *__restrict__ ranges, CamK c, float bg0,
+                                                     float bg1, float bg2, const float *__restrict__ final_T,
+                                                     const uint32_t *__restrict__ ncontrib,
+                                                     const float *__restrict__ dL, float4 *__restrict__ ig,
+                                                     uint32_t capacity, int ntiles, int per_xcd) {
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * per_xcd + (b >> 3);
+    if (tile >= ntiles) return;
+    const int tx = tile % c.TX, ty = tile / c.TX;
+    const int ln = lane_id();
+    const int px = tx * kTile + (ln & 15);
+    const size_t plane = (size_t)c.W * c.H;
+    const float sx = (float)px + 0.5f;
+    float sy[kPx], Tc[kPx], S0[kPx], S1[kPx], S2[kPx], g0[kPx], g1[kPx], g2[kPx];
+    uint32_t nc[kPx];
+    uint32_t nmax = 0;
+#pragma unroll
+    for (int k = 0; k < kPx; ++k) {
+        const int py = ty * kTile + (ln >> 4) + 4 * k;
+        sy[k] = (float)py + 0.5f;
+        const bool in = px < c.W && py < c.H;
+        const size_t pi = (size_t)py * c.W + px;
+        Tc[k] = in ? final_T[pi] : 1.0f;
+        nc[k] = in ? ncontrib[pi] : 0u;
+        g0[k] = in ? dL[pi] : 0.0f;
+        g1[k] = in ? dL[plane + pi] : 0.0f;
+        g2[k] = in ? dL[2 * plane + pi] : 0.0f;
+        S0[k] = Tc[k] * bg0;
+        S1[k] = Tc[k] * bg1;
+        S2[k] = Tc[k] * bg2;
+        nmax = max(nmax, nc[k]);
+    }
+    nmax = __builtin_amdgcn_readfirstlane(wave_max_u32(nmax));
+    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    // instances behind every pixel's last contributor get zero gradients
+    for (uint32_t j = start + nmax + ln; j < end; j += kWave) {
+        const uint32_t slot = inst_slot(rec, offset, vals[j], tx, ty);
+        if (slot >= capacity) continue;  // only after an instance overflow
+        ig[3 * (size_t)slot + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+        ig[3 * (size_t)slot + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        ig[3 * (size_t)slot + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    for (uint32_t jj = nmax; jj-- > 0;) {
+        const uint32_t j = start + jj;
+        const uint32_t gi = vals[j];
+        const SplatK s = load_splat(rec, gi);
+        const float4 r0 = rec[3 * (size_t)gi + 0];
+        const float cA = r0.z, cB = r0.w, cC = rec[3 * (size_t)gi + 1].x;
+        float a_mx = 0.f, a_my = 0.f, a_A = 0.f, a_B = 0.f, a_C = 0.f, a_am = 0.f, a_r = 0.f, a_g = 0.f, a_b = 0.f;
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kPx; ++k) {
+            const float dx = sx - s.mx, dy = sy[k] - s.my;
+            const float q = splat_exponent(s, dx, dy);
+            const float G = exp2_fast(q);
+            const float araw = s.amax * G;
+            const float alpha = fminf(kAlphaMax, araw);
+            const bool ok = jj < nc[k] && q <= 0.0f && alpha >= kAlphaMin;
+            if (ok) {
+                any = true;
+                const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                const float Ti = Tc[k] * inv;
+                const float da = g0[k] * (s.r * Ti - S0[k] * inv) + g1[k] * (s.g * Ti - S1[k] * inv) +
+                                 g2[k] * (s.b * Ti - S2[k] * inv);
+                const float wgt = alpha * Ti;
+                a_r += g0[k] * wgt;
+                a_g += g1[k] * wgt;
+                a_b += g2[k] * wgt;
+                S0[k] += s.r * wgt;
+                S1[k] += s.g * wgt;
+                S2[k] += s.b * wgt;
+                Tc[k] = Ti;
+                if (araw <= kAlphaMax) {
+                    const float dp = da * alpha;  // d/d(power), power the natural-log exponent
+                    a_am += da * G;
+                    a_mx += dp * (cA * dx + cB * dy);
+                    a_my += dp * (cC * dy + cB * dx);
+                    a_A += dp * (-0.5f * dx * dx);
+                    a_B += dp * (-(dx * dy));
+                    a_C += dp * (-0.5f * dy * dy);
+                }
+            }
+        }
+        const uint32_t slot = inst_slot(rec, offset, gi, tx, ty);
+        const bool slot_ok = slot < capacity;  // false only after an instance overflow
+        if (__ballot(any) == 0) {
+            if (ln == 0 && slot_ok) {
+                ig[3 * (size_t)slot + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+                ig[3 * (size_t)slot + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+                ig[3 * (size_t)slot + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            continue;
+        }
+        a_mx = wave_sum(a_mx);
+        a_my = wave_sum(a_my);
+        a_A = wave_sum(a_A);
+        a_B = wave_sum(a_B);
+        a_C = wave_sum(a_C);
+        a_am = wave_sum(a_am);
+        a_r = wave_sum(a_r);
+        a_g = wave_sum(a_g);
+        a_b = wave_sum(a_b);
+        if (ln == 0 && slot_ok) {
+            ig[3 * (size_t)slot + 0] = make_float4(a_mx, a_my, a_A, a_B);
+            ig[3 * (size_t)slot + 1] = make_float4(a_C, a_am, a_r, a_g);
+            ig[3 * (size_t)slot + 2] = make_float4(a_b, 0.f, 0.f, 0.f);
+        }
+    }
+}
+
+// d Y_k / d(x, y, z) of the polynomial basis used in the forward (any extension of
+// Y_k off the unit sphere works: the radial part is projected out afterwards).
+template <int DEG>
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, float Y[16], float dY[16][3]) {
+    const float C0 = 0.28209479177387814f, C1 = 0.4886025119029199f;
+    const float C2a = 1.0925484305920792f, C2b = 0.31539156525252005f, C2c = 0.5462742152960396f;
+    const float C3a = -0.5900435899266435f, C3b = 2.890611442640554f, C3c = -0.4570457994644658f;
+    const float C3d = 0.3731763325901154f, C3e = 1.445305721320277f;
+    Y[0] = C0;
+    dY[0][0] = dY[0][1] = dY[0][2] = 0.f;
+    if (DEG >= 1) {
+        Y[1] = -C1 * y; dY[1][0] = 0.f; dY[1][1] = -C1; dY[1][2] = 0.f;
+        Y[2] = C1 * z;  dY[2][0] = 0.f; dY[2][1] = 0.f; dY[2][2] = C1;
+        Y[3] = -C1 * x; dY[3][0] = -C1; dY[3][1] = 0.f; dY[3][2] = 0.f;
+    }
+    if (DEG >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = C2a * (x * y);       dY[4][0] = C2a * y;  dY[4][1] = C2a * x;  dY[4][2] = 0.f;
+        Y[5] = -C2a * (y * z);      dY[5][0] = 0.f;      dY[5][1] = -C2a * z; dY[5][2] = -C2a * y;
+        Y[6] = C2b * (3.f * zz - 1.f); dY[6][0] = 0.f;   dY[6][1] = 0.f;      dY[6][2] = 6.f * C2b * z;
+        Y[7] = -C2a * (x * z);      dY[7][0] = -C2a * z; dY[7][1] = 0.f;      dY[7][2] = -C2a * x;
+        Y[8] = C2c * (xx - yy);     dY[8][0] = 2.f * C2c * x; dY[8][1] = -2.f * C2c * y; dY[8][2] = 0.f;
+        if (DEG >= 3) {
+            Y[9] = C3a * y * (3.f * xx - yy);
+            dY[9][0] = C3a * 6.f * x * y; dY[9][1] = C3a * (3.f * xx - 3.f * yy); dY[9][2] = 0.f;
+            Y[10] = C3b * (x * y) * z;
+            dY[10][0] = C3b * y * z; dY[10][1] = C3b * x * z; dY[10][2] = C3b * x * y;
+            Y[11] = C3c * y * (5.f * zz - 1.f);
+            dY[11][0] = 0.f; dY[11][1] = C3c * (5.f * zz - 1.f); dY[11][2] = C3c * 10.f * y * z;
+            Y[12] = C3d * z * (5.f * zz - 3.f);
+            dY[12][0] = 0.f; dY[12][1] = 0.f; dY[12][2] = C3d * (15.f * zz - 3.f);
+            Y[13] = C3c * x * (5.f * zz - 1.f);
+            dY[13][0] = C3c * (5.f * zz - 1.f); dY[13][1] = 0.f; dY[13][2] = C3c * 10.f * x * z;
+            Y[14] = C3e * z * (xx - yy);
+            dY[14][0] = 2.f * C3e * x * z; dY[14][1] = -2.f * C3e * y * z; dY[14][2] = C3e * (xx - yy);
+            Y[15] = C3a * x * (xx - 3.f * yy);
+            dY[15][0] = C3a * (3.f * xx - 3.f * yy); dY[15][1] = -6.f * C3a * x * y; dY[15][2] = 0.f;
+        }
+    }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float t, const float4 *__restrict__ rec,
+                                                        const uint32_t *__restrict__ count,
+                                                        const uint32_t *__restrict__ offset,
+                                                        const float4 *__restrict__ ig, uint32_t capacity,
+                                                        d4dgs_grads out) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int gi = blockIdx.x * kBlock + threadIdx.x;
+    const int n = s.n;
+    if (gi >= n) return;
+    const uint32_t cnt = count[gi];
+    if (cnt == 0) return;
+    if ((uint64_t)offset[gi] + cnt > capacity) return;  // instances lost to an overflow
+    // 1. sum this Gaussian's instance gradients in emission order
+    float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gam = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
+    const uint32_t o0 = offset[gi];
+    for (uint32_t k = 0; k < cnt; ++k) {
+        const size_t sl = 3 * (size_t)(o0 + k);
+        const float4 a = ig[sl], b4 = ig[sl + 1], c4 = ig[sl + 2];
+        gmx += a.x; gmy += a.y; gA += a.z; gB += a.w;
+        gC += b4.x; gam += b4.y; gr += b4.z; gg += b4.w;
+        gb += c4.x;
+    }
+    // 2. recompute the forward quantities (camera stage + time stage)
+    const float q0 = s.quat[gi], q1 = s.quat[n + gi], q2 = s.quat[2 * n + gi], q3 = s.quat[3 * n + gi];
+    const float n2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
+    const float nrm = sqrtf(n2);
+    const float qw = q0 / nrm, qx = q1 / nrm, qy = q2 / nrm, qz = q3 / nrm;
+    float Rq[9];
+    Rq[0] = 1.0f - 2.0f * (qy * qy + qz * qz);
+    Rq[1] = 2.0f * (qx * qy - qw * qz);
+    Rq[2] = 2.0f * (qx * qz + qw * qy);
+    Rq[3] = 2.0f * (qx * qy + qw * qz);
+    Rq[4] = 1.0f - 2.0f * (qx * qx + qz * qz);
+    Rq[5] = 2.0f * (qy * qz - qw * qx);
+    Rq[6] = 2.0f * (qx * qz - qw * qy);
+    Rq[7] = 2.0f * (qy * qz + qw * qx);
+    Rq[8] = 1.0f - 2.0f * (qx * qx + qy * qy);
+    const float sc[3] = {s.scale[gi], s.scale[n + gi], s.scale[2 * n + gi]};
+    float M[9], Sg[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[3 * i + j] = Rq[3 * i + j] * sc[j];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            Sg[3 * i + j] = M[3 * i + 0] * M[3 * j + 0] + M[3 * i + 1] * M[3 * j + 1] + M[3 * i + 2] * M[3 * j + 2];
+    const float mu[3] = {s.mean[gi], s.mean[n + gi], s.mean[2 * n + gi]};
+    const float v[3] = {s.velocity[gi], s.velocity[n + gi], s.velocity[2 * n + gi]};
+    const float *R = c.R;
+    float p[3], u[3];
+    for (int i = 0; i < 3; ++i) {
+        p[i] = R[3 * i + 0] * mu[0] + R[3 * i + 1] * mu[1] + R[3 * i + 2] * mu[2] + c.T[i];
+        u[i] = R[3 * i + 0] * v[0] + R[3 * i + 1] * v[1] + R[3 * i + 2] * v[2];
+    }
+    float A3[9], V[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            A3[3 * i + j] = R[3 * i + 0] * Sg[j] + R[3 * i + 1] * Sg[3 + j] + R[3 * i + 2] * Sg[6 + j];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            V[3 * i + j] = A3[3 * i + 0] * R[3 * j + 0] + A3[3 * i + 1] * R[3 * j + 1] + A3[3 * i + 2] * R[3 * j + 2];
+    const float op = s.opacity[gi], mut = s.t_mean[gi], st = s.t_scale[gi];
+    const float tau = t - mut;
+    const float w = expf(-0.5f * ((tau * tau) / (st * st)));
+    const float pt[3] = {p[0] + tau * u[0], p[1] + tau * u[1], p[2] + tau * u[2]};
+    const float md[2] = {(c.fx * u[0]) / p[2], (c.fy * u[1]) / p[2]};
+    const float z = pt[2];
+    float rx = pt[0] / z, ry = pt[1] / z;
+    const bool clx = rx > c.limx || rx < -c.limx, cly = ry > c.limy || ry < -c.limy;
+    rx = fminf(c.limx, fmaxf(-c.limx, rx));
+    ry = fminf(c.limy, fmaxf(-c.limy, ry));
+    const float tx = rx * z, ty = ry * z;
+    const float J00 = c.fx / z, J11 = c.fy / z;
+    const float J02 = -(c.fx * tx) / (z * z), J12 = -(c.fy * ty) / (z * z);
+    // conic (A, B, C) of the record
+    const float4 r0 = rec[3 * (size_t)gi], r1 = rec[3 * (size_t)gi + 1];
+    const float QA = r0.z, QB = r0.w, QC = r1.x;
+
+    // 3. chain rule, time stage
+    float g_o = w * gam;
+    const float g_w = op * gam;
+    float g_tau = g_w * (-w * tau / (st * st));
+    float g_st = g_w * (w * tau * tau / (st * st * st));
+    // conic = inverse(S2), S2 = [[a, b], [b, c]]:  dS2 = -Q dQ Q
+    const float h = 0.5f * gB;
+    const float g_a = -(QA * QA * gA + 2.f * QA * QB * h + QB * QB * gC);
+    const float g_c = -(QB * QB * gA + 2.f * QB * QC * h + QC * QC * gC);
+    const float g_b2 = -(QA * QB * gA + (QB * QB + QA * QC) * h + QB * QC * gC);  // half of d/db
+    // Sigma' = J V J^T with gradient matrix Gp = [[g_a, g_b2], [g_b2, g_c]]
+    const float J[2][3] = {{J00, 0.f, J02}, {0.f, J11, J12}};
+    const float Gp[2][2] = {{g_a, g_b2}, {g_b2, g_c}};
+    // g_V = J^T Gp J
+    float GJ[2][3];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j) GJ[i][j] = Gp[i][0] * J[0][j] + Gp[i][1] * J[1][j];
+    float gV[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) gV[3 * i + j] = J[0][i] * GJ[0][j] + J[1][i] * GJ[1][j];
+    // g_J = 2 Gp J V
+    float JV[2][3];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j) JV[i][j] = J[i][0] * V[j] + J[i][1] * V[3 + j] + J[i][2] * V[6 + j];
+    float gJ[2][3];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j) gJ[i][j] = 2.f * (Gp[i][0] * JV[0][j] + Gp[i][1] * JV[1][j]);
+    const float z2 = z * z, z3 = z2 * z;
+    float g_pt[3] = {0.f, 0.f, 0.f};
+    g_pt[2] += gJ[0][0] * (-c.fx / z2) + gJ[0][2] * (2.f * c.fx * tx / z3) + gJ[1][1] * (-c.fy / z2) +
+               gJ[1][2] * (2.f * c.fy * ty / z3);
+    const float g_tx = gJ[0][2] * (-c.fx / z2), g_ty = gJ[1][2] * (-c.fy / z2);
+    if (clx) g_pt[2] += g_tx * rx; else g_pt[0] += g_tx;
+    if (cly) g_pt[2] += g_ty * ry; else g_pt[1] += g_ty;
+    // p_t = p + tau u ; m = m0 + tau md
+    float g_p[3], g_u[3];
+    for (int i = 0; i < 3; ++i) {
+        g_p[i] = g_pt[i];
+        g_u[i] = tau * g_pt[i];
+    }
+    g_tau += u[0] * g_pt[0] + u[1] * g_pt[1] + u[2] * g_pt[2];
+    g_tau += md[0] * gmx + md[1] * gmy;
+    const float g_mdx = tau * gmx, g_mdy = tau * gmy;
+    // camera stage: m0 = f p_xy / p_z + c ; md = f u_xy / p_z
+    const float ipz = 1.f / p[2];
+    g_p[0] += c.fx * gmx * ipz;
+    g_p[1] += c.fy * gmy * ipz;
+    g_p[2] += -(c.fx * p[0] * gmx + c.fy * p[1] * gmy) * ipz * ipz;
+    g_u[0] += c.fx * g_mdx * ipz;
+    g_u[1] += c.fy * g_mdy * ipz;
+    g_p[2] += -(c.fx * u[0] * g_mdx + c.fy * u[1] * g_mdy) * ipz * ipz;
+    // p = R mu + T, u = R v
+    float g_mu[3], g_v[3];
+    for (int j = 0; j < 3; ++j) {
+        g_mu[j] = R[j] * g_p[0] + R[3 + j] * g_p[1] + R[6 + j] * g_p[2];
+        g_v[j] = R[j] * g_u[0] + R[3 + j] * g_u[1] + R[6 + j] * g_u[2];
+    }
+    // V = R Sigma R^T  ->  g_Sigma = R^T gV R
+    float tmp[9], gS[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) tmp[3 * i + j] = R[i] * gV[j] + R[3 + i] * gV[3 + j] + R[6 + i] * gV[6 + j];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) gS[3 * i + j] = tmp[3 * i + 0] * R[j] + tmp[3 * i + 1] * R[3 + j] + tmp[3 * i + 2] * R[6 + j];
+    // Sigma = M M^T -> g_M = (gS + gS^T) M
+    float gM[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            float acc = 0.f;
+            for (int k = 0; k < 3; ++k) acc += (gS[3 * i + k] + gS[3 * k + i]) * M[3 * k + j];
+            gM[3 * i + j] = acc;
+        }
+    float g_s[3], gRq[9];
+    for (int j = 0; j < 3; ++j) g_s[j] = gM[j] * Rq[j] + gM[3 + j] * Rq[3 + j] + gM[6 + j] * Rq[6 + j];
+    for (int i = 0; i < 9; ++i) gRq[i] = gM[i] * sc[i % 3];
+    // rotation matrix of the unit quaternion (w, x, y, z)
+    float gqw = 2.f * (-qz * gRq[1] + qy * gRq[2] + qz * gRq[3] - qx * gRq[5] - qy * gRq[6] + qx * gRq[7]);
+    float gqx = 2.f * (qy * gRq[1] + qz * gRq[2] + qy * gRq[3] - 2.f * qx * gRq[4] - qw * gRq[5] + qz * gRq[6] +
+                       qw * gRq[7] - 2.f * qx * gRq[8]);
+    float gqy = 2.f * (-2.f * qy * gRq[0] + qx * gRq[1] + qw * gRq[2] + qx * gRq[3] + qz * gRq[5] - qw * gRq[6] +
+                       qz * gRq[7] - 2.f * qy * gRq[8]);
+    float gqz = 2.f * (-2.f * qz * gRq[0] - qw * gRq[1] + qx * gRq[2] + qw * gRq[3] - 2.f * qz * gRq[4] +
+                       qy * gRq[5] + qx * gRq[6] + qy * gRq[7]);
+    const float dotq = qw * gqw + qx * gqx + qy * gqy + qz * gqz;
+    const float g_q[4] = {(gqw - qw * dotq) / nrm, (gqx - qx * dotq) / nrm, (gqy - qy * dotq) / nrm,
+                          (gqz - qz * dotq) / nrm};
+    // colour: rgb = max(0, sum_k Y_k(d) sh_k + 0.5), d = (mu - campos) / |mu - campos|
+    {
+        const float dx0 = mu[0] - c.campos[0], dy0 = mu[1] - c.campos[1], dz0 = mu[2] - c.campos[2];
+        const float len = sqrtf(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
+        const float d[3] = {dx0 / len, dy0 / len, dz0 / len};
+        float Y[16], dY[16][3];
+        sh_basis_grad<DEG>(d[0], d[1], d[2], Y, dY);
+        const float grgb[3] = {gr, gg, gb};
+        float g_d[3] = {0.f, 0.f, 0.f};
+        for (int ch = 0; ch < 3; ++ch) {
+            float raw = 0.5f;
+            for (int k = 0; k < K; ++k) raw += Y[k] * s.sh[(size_t)(k * 3 + ch) * n + gi];
+            if (raw < 0.f) continue;
+            for (int k = 0; k < K; ++k) {
+                const size_t idx = (size_t)(k * 3 + ch) * n + gi;
+                out.sh[idx] += Y[k] * grgb[ch];
+                const float f = s.sh[idx] * grgb[ch];
+                g_d[0] += f * dY[k][0];
+                g_d[1] += f * dY[k][1];
+                g_d[2] += f * dY[k][2];
+            }
+        }
+        const float dd = d[0] * g_d[0] + d[1] * g_d[1] + d[2] * g_d[2];
+        for (int i = 0; i < 3; ++i) g_mu[i] += (g_d[i] - d[i] * dd) / len;
+    }
+    for (int i = 0; i < 3; ++i) {
+        out.mean[i * n + gi] += g_mu[i];
+        out.scale[i * n + gi] += g_s[i];
+        out.velocity[i * n + gi] += g_v[i];
+    }
+    for (int i = 0; i < 4; ++i) out.quat[i * n + gi] += g_q[i];
+    out.opacity[gi] += g_o;
+    out.t_mean[gi] += -g_tau;
+    out.t_scale[gi] += g_st;
+    (void)g_o;
+}
+
+}  // namespace
+
+hipError_t launch_blend_bwd(const float4 *rec, const uint32_t *offset, const uint32_t *vals, const uint32_t *ranges,
+                            const CamK &c, const float bg[3], const float *final_T, const uint32_t *n_contrib,
+                            const float *dL_dimg, float4 *inst_grads, int64_t capacity, hipStream_t st) {
+    const int ntiles = c.TX * c.TY;
+    if (ntiles == 0) return hipSuccess;
+    const int per_xcd = (ntiles + 7) / 8;
+    hipLaunchKernelGGL(k_blend_bwd, dim3(per_xcd * 8), dim3(kWave), 0, st, rec, offset, vals, ranges, c, bg[0], bg[1],
+                       bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, ntiles, per_xcd);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const SceneK &s, const CamK &c, float t, const float4 *rec, const uint32_t *count,
+                              const uint32_t *offset, const float4 *inst_grads, int64_t capacity,
+                              const d4dgs_grads &g, hipStream_t st) {
+    if (s.n == 0) return hipSuccess;
+    const int grid = (s.n + kBlock - 1) / kBlock;
+    switch (s.deg) {
+        case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g); break;
+        default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace d4

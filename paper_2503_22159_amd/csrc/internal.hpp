@@ -1,0 +1,144 @@
+// Internal declarations shared by the HIP translation units of libd4dgs (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "d4dgs.h"
+
+namespace d4 {
+
+constexpr int kWave = 64;
+constexpr int kTile = D4DGS_TILE;
+constexpr int kBlock = 256;             // threads per block of the per-Gaussian kernels
+constexpr int kRadixBits = 8;           // LSD digit width
+constexpr int kRadix = 1 << kRadixBits; // buckets per pass
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                         // keys per thread per chunk
+constexpr int kSortChunk = kSortThreads * kSortItems;  // keys per chunk (4096)
+constexpr int kSortGrid = 1024;  // blocks of the chunk-looping sort kernels
+
+// fp32(2 ln 255): a Gaussian with tau^2 > kTemporalCull * s_t^2 has w < 1/255 and is culled.
+constexpr float kTemporalCull = 11.0825272f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr float kDilation = 0.3f;
+constexpr float kGuard = 1.3f;
+constexpr float kLog2e = 1.44269504088896340736f;
+
+// Camera as passed to kernels (by value).
+struct CamK {
+    float R[9], T[3], campos[3];
+    float fx, fy, cx, cy;
+    float limx, limy, znear;
+    int W, H, TX, TY;
+};
+
+CamK make_camk(const d4dgs_camera &c);
+
+// --- wave64 helpers ---------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (uint64_t(1) << lane_id()) - 1;  // lane 0 -> 0
+}
+
+// inclusive prefix sum over the wave (Hillis-Steele with cross-lane shuffles)
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t u = __shfl_up(v, o, kWave);
+        if (lane_id() >= o) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, kWave));
+    return v;
+}
+
+// The blend's per-(pixel, splat) opacity, shared bit-for-bit by forward and backward.
+// Folded exponent: q = log2(e) * (-1/2 (a dx^2 + c dy^2) - b dx dy) computed as
+// (qa dx + qb dy) dx + qc dy dy with qa = -log2(e)/2 a, qb = -log2(e) b, qc = -log2(e)/2 c.
+struct SplatK {
+    float mx, my, qa, qb, qc, amax, r, g, b;
+};
+
+__device__ __forceinline__ SplatK load_splat(const float4 *__restrict__ rec, uint32_t gi) {
+    const float4 p = rec[3 * gi + 0];
+    const float4 q = rec[3 * gi + 1];
+    const float4 s = rec[3 * gi + 2];
+    SplatK k;
+    k.mx = p.x;
+    k.my = p.y;
+    k.qa = (-0.5f * kLog2e) * p.z;
+    k.qb = (-kLog2e) * p.w;
+    k.qc = (-0.5f * kLog2e) * q.x;
+    k.amax = q.y;
+    k.r = q.z;
+    k.g = q.w;
+    k.b = s.x;
+    return k;
+}
+
+__device__ __forceinline__ float splat_exponent(const SplatK &k, float dx, float dy) {
+    return __builtin_fmaf(__builtin_fmaf(k.qa, dx, k.qb * dy), dx, (k.qc * dy) * dy);
+}
+
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// --- launchers (host side) ----------------------------------------------------------
+struct SceneK {
+    int n, deg;
+    const float *mean, *scale, *quat, *opacity, *t_mean, *t_scale, *velocity, *sh;
+};
+
+SceneK make_scenek(const d4dgs_scene &s);
+
+// mode 0: camera + time stage, no record; 1: camera + time stage, writes record; 2: time stage from record
+hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, float *cam_rec, int cam_cap,
+                          float4 *rec, uint32_t *count, uint32_t *block_sums, hipStream_t st);
+
+struct SortWs {
+    uint32_t *block_sums;  // unused (the per-block sums live in d4dgs_splats::partial)
+    uint64_t *alt_keys;    // capacity
+    uint32_t *alt_vals;    // capacity
+    uint32_t *hist;        // kRadix * max_chunks
+    uint32_t *misc;        // small scalars
+    int64_t max_chunks;
+};
+
+size_t sort_workspace_bytes(int n, int64_t capacity);
+SortWs carve_workspace(void *ws, int n, int64_t capacity);
+int sort_passes(int tiles);
+
+hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *offset, uint32_t *partial, int n,
+                           const CamK &c, const SortWs &ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
+                           int64_t *num_inst, int64_t capacity, int32_t *d_status, hipStream_t st);
+
+hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c,
+                        const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st);
+
+hipError_t launch_blend_bwd(const float4 *rec, const uint32_t *offset, const uint32_t *vals,
+                            const uint32_t *ranges, const CamK &c, const float bg[3], const float *final_T,
+                            const uint32_t *n_contrib, const float *dL_dimg, float4 *inst_grads,
+                            int64_t capacity, hipStream_t st);
+
+hipError_t launch_project_bwd(const SceneK &s, const CamK &c, float t, const float4 *rec, const uint32_t *count,
+                              const uint32_t *offset, const float4 *inst_grads, int64_t capacity,
+                              const d4dgs_grads &g, hipStream_t st);
+
+void set_error(const std::string &msg);
+
+}  // namespace d4

@@ -1,0 +1,241 @@
+"""PyTorch-facing wrappers of libd4dgs.
+
+PyTorch supplies device memory and the current HIP stream; every stage of the render
+path runs in the library's kernels (binding.py marshals arguments only).
+
+    scene = DeviceScene.from_inputs(inputs_scene)          # resident parameters
+    img, state = render_forward(scene, cam, t, bg)          # project -> bin/sort -> blend
+    grads = render_backward(scene, cam, t, bg, state, dL)   # adjoint, all parameters
+    img = render(params..., cam=..., t=...)                 # autograd.Function
+    r = Renderer(scene, width, height); r.render(cam, t)    # fixed buffers for loops
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+FIELDS = ("mean", "scale", "quat", "opacity", "t_mean", "t_scale", "velocity", "sh")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def tiles_of(width, height):
+    return ((width + B.TILE - 1) // B.TILE) * ((height + B.TILE - 1) // B.TILE)
+
+
+def default_capacity(n, width, height):
+    """Instance capacity: enough for the synthetic workloads' overlap (about 4 tiles per
+    Gaussian) with headroom; render_forward grows it on overflow."""
+    return int(max(1 << 16, 4 * n, 2 * tiles_of(width, height)))
+
+
+class DeviceScene:
+    """Scene parameters on the GPU: planar float32 tensors (see inputs.Scene)."""
+
+    def __init__(self, tensors: dict, sh_degree: int):
+        self.t = {k: tensors[k].contiguous() for k in FIELDS}
+        for k in FIELDS:
+            assert self.t[k].dtype == torch.float32 and self.t[k].is_cuda, k
+        self.n = int(self.t["opacity"].shape[0])
+        self.sh_degree = int(sh_degree)
+
+    @classmethod
+    def from_inputs(cls, scene, device="cuda"):
+        return cls({k: torch.from_numpy(np.ascontiguousarray(getattr(scene, k))).to(device) for k in FIELDS},
+                   scene.sh_degree)
+
+    def struct(self):
+        s = B.Scene()
+        s.n = self.n
+        s.sh_degree = self.sh_degree
+        for k in FIELDS:
+            setattr(s, k, self.t[k].data_ptr())
+        return s
+
+
+class FrameState:
+    """Device buffers of one rendered frame (splat record, sorted bins, replay state)."""
+
+    def __init__(self, n, width, height, capacity, device="cuda"):
+        self.n, self.width, self.height, self.capacity = n, width, height, int(capacity)
+        dev = device
+        nn = max(n, 1)
+        self.rec = torch.empty(nn * B.REC_FLOATS, dtype=torch.float32, device=dev)
+        self.count = torch.empty(nn, dtype=torch.int32, device=dev)
+        self.offset = torch.empty(nn, dtype=torch.int32, device=dev)
+        self.partial = torch.empty((nn + 255) // 256, dtype=torch.int32, device=dev)
+        self.keys = torch.empty(self.capacity, dtype=torch.int64, device=dev)
+        self.values = torch.empty(self.capacity, dtype=torch.int32, device=dev)
+        self.ranges = torch.empty(2 * tiles_of(width, height), dtype=torch.int32, device=dev)
+        self.num_inst = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ws = torch.empty(B.workspace_size(n, width, height, self.capacity), dtype=torch.uint8, device=dev)
+        self.img = None
+        self.final_T = None
+        self.n_contrib = None
+
+    def splats(self):
+        s = B.Splats()
+        s.capacity = max(self.n, 1)
+        s.rec, s.count, s.offset, s.partial = (self.rec.data_ptr(), self.count.data_ptr(),
+                                               self.offset.data_ptr(), self.partial.data_ptr())
+        return s
+
+    def bins(self):
+        b = B.Bins()
+        b.capacity = self.capacity
+        b.keys, b.values, b.ranges, b.num_instances = (self.keys.data_ptr(), self.values.data_ptr(),
+                                                       self.ranges.data_ptr(), self.num_inst.data_ptr())
+        return b
+
+
+class CamCache:
+    """Device buffer + bookkeeping of the camera-stage cache (Alg. 1)."""
+
+    def __init__(self, capacity, device="cuda"):
+        self.buf = torch.empty(max(capacity, 1) * B.CAM_REC_FLOATS, dtype=torch.float32, device=device)
+        self.c = B.CamCache()
+        self.c.rec = self.buf.data_ptr()
+        self.c.capacity = max(capacity, 1)
+        self.c.valid = 0
+
+    def invalidate(self):
+        self.c.valid = 0
+
+
+def _bg(bg):
+    a = (C.c_float * 3)()
+    for i in range(3):
+        a[i] = float(bg[i])
+    return a
+
+
+def project(scene: DeviceScene, cam, t, st: FrameState, cache: CamCache | None = None):
+    s = scene.struct()
+    sp = st.splats()
+    B.check(B.lib.d4dgs_project(C.byref(s), C.byref(B.camera_struct(cam)), float(t),
+                                C.byref(cache.c) if cache is not None else None, C.byref(sp), _stream()))
+
+
+def bin_sort(st: FrameState, sync=False):
+    sp, bn = st.splats(), st.bins()
+    if sync:
+        ni = C.c_int64(0)
+        r = B.lib.d4dgs_bin_sort_sync(C.byref(sp), st.n, st.width, st.height, _ptr(st.ws), st.ws.numel(),
+                                      C.byref(bn), C.byref(ni), _stream())
+        if r == B.ERR_CAPACITY:
+            return int(ni.value)
+        B.check(r)
+        return int(ni.value)
+    B.check(B.lib.d4dgs_bin_sort(C.byref(sp), st.n, st.width, st.height, _ptr(st.ws), st.ws.numel(), C.byref(bn),
+                                 _ptr(st.status), _stream()))
+    return None
+
+
+def blend(st: FrameState, bg=(0.0, 0.0, 0.0), keep_state=True, img=None):
+    H, W = st.height, st.width
+    dev = st.rec.device
+    st.img = img if img is not None else torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    if keep_state:
+        st.final_T = torch.empty((H, W), dtype=torch.float32, device=dev)
+        st.n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
+    sp, bn = st.splats(), st.bins()
+    B.check(B.lib.d4dgs_render_fwd(C.byref(sp), C.byref(bn), W, H, C.byref(_bg(bg)), _ptr(st.img),
+                                   _ptr(st.final_T) if keep_state else None,
+                                   _ptr(st.n_contrib) if keep_state else None, _stream()))
+    return st.img
+
+
+def render_forward(scene: DeviceScene, cam, t, bg=(0.0, 0.0, 0.0), capacity=None, keep_state=True,
+                   cache: CamCache | None = None):
+    """Full forward with exact instance capacity handling (synchronises once to read the
+    instance count; grows the capacity and re-sorts on overflow)."""
+    cap = capacity or default_capacity(scene.n, cam.width, cam.height)
+    st = FrameState(scene.n, cam.width, cam.height, cap, scene.t["mean"].device)
+    project(scene, cam, t, st, cache)
+    ni = bin_sort(st, sync=True)
+    if ni > st.capacity:
+        # the scan consumed the per-block sums in place: project again into larger buffers
+        st = FrameState(scene.n, cam.width, cam.height, int(ni * 1.25) + 1024, scene.t["mean"].device)
+        project(scene, cam, t, st, cache)
+        ni2 = bin_sort(st, sync=True)
+        assert ni2 == ni
+    st.num_instances = ni
+    img = blend(st, bg, keep_state)
+    return img, st
+
+
+def grads_like(scene: DeviceScene):
+    return {k: torch.zeros_like(scene.t[k]) for k in FIELDS}
+
+
+def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, grads=None):
+    """Adds d(sum dL_dimg * img)/d(params) into `grads` (created zeroed if None)."""
+    if grads is None:
+        grads = grads_like(scene)
+    dL = dL_dimg.contiguous().float()
+    st.inst_grads = torch.empty(max(st.capacity, 1) * B.GRAD_FLOATS, dtype=torch.float32, device=dL.device)
+    g = B.Grads()
+    for k in FIELDS:
+        setattr(g, k, grads[k].data_ptr())
+    s = scene.struct()
+    B.check(B.lib.d4dgs_render_bwd(C.byref(s), C.byref(B.camera_struct(cam)), float(t), C.byref(st.splats()),
+                                   C.byref(st.bins()), C.byref(_bg(bg)), _ptr(st.final_T), _ptr(st.n_contrib),
+                                   _ptr(dL), _ptr(st.inst_grads), C.byref(g), _stream()))
+    return grads
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, cam, t, bg, sh_degree, capacity, *params):
+        scene = DeviceScene(dict(zip(FIELDS, [p.detach() for p in params])), sh_degree)
+        img, st = render_forward(scene, cam, t, bg, capacity)
+        ctx.scene, ctx.cam, ctx.t, ctx.bg, ctx.st = scene, cam, t, bg, st
+        return img
+
+    @staticmethod
+    def backward(ctx, dL_dimg):
+        g = render_backward(ctx.scene, ctx.cam, ctx.t, ctx.bg, ctx.st, dL_dimg)
+        return (None, None, None, None, None) + tuple(g[k] for k in FIELDS)
+
+
+def render(mean, scale, quat, opacity, t_mean, t_scale, velocity, sh, *, cam, t, sh_degree, bg=(0.0, 0.0, 0.0),
+           capacity=None):
+    """Differentiable render of one (camera, t) view; gradients flow to all eight
+    parameter tensors (planar layout, float32, CUDA)."""
+    return _RenderFn.apply(cam, float(t), tuple(bg), int(sh_degree), capacity, mean, scale, quat, opacity, t_mean,
+                           t_scale, velocity, sh)
+
+
+class Renderer:
+    """Fixed device buffers for repeated frames of one resolution (timing loops,
+    sweeps).  Fully asynchronous: no host synchronisation per frame."""
+
+    def __init__(self, scene: DeviceScene, width, height, capacity=None, cache=True, keep_state=False):
+        self.scene = scene
+        self.width, self.height = int(width), int(height)
+        self.st = FrameState(scene.n, self.width, self.height,
+                             capacity or default_capacity(scene.n, width, height), scene.t["mean"].device)
+        self.cache = CamCache(scene.n, scene.t["mean"].device) if cache else None
+        self.keep_state = keep_state
+        self.img = torch.empty((3, self.height, self.width), dtype=torch.float32, device=scene.t["mean"].device)
+
+    def render(self, cam, t, bg=(0.0, 0.0, 0.0)):
+        assert cam.width == self.width and cam.height == self.height
+        project(self.scene, cam, t, self.st, self.cache)
+        bin_sort(self.st)
+        return blend(self.st, bg, self.keep_state, img=self.img)
+
+    def overflowed(self):
+        """True if any frame since the last reset exceeded the instance capacity."""
+        return int(self.st.status.item()) != 0

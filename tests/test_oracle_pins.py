@@ -385,6 +385,22 @@ def test_p9_binning_bruteforce(oracle_lib):
                               (np.uint64(tile) << np.uint64(32)) | dbits[sel].astype(np.uint64))
 
 
+def test_results_independent_of_thread_count(oracle_lib):
+    """The oracle's projection, bins and image do not depend on its OpenMP thread count
+    (a lazily built shared table once raced under 16 threads)."""
+    sc = inputs.config2_scene(n=4000)
+    cam = inputs.arc_camera(5, width=96, height=80)
+    outs = []
+    for nt in (1, 3, 16, 0):
+        oracle_lib.set_threads(nt)
+        proj, bins, res = oracle_lib.render(sc, cam, np.float32(0.4))
+        outs.append((proj["rgb"].copy(), bins["values"].copy(), res["img"].copy()))
+    oracle_lib.set_threads(0)
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
 def test_fp32_and_fp64_decisions_agree(oracle_lib):
     """The FP32 contract path and the FP64 path take the same tile decisions on config 1
     (differences could only come from values within rounding of a boundary)."""
