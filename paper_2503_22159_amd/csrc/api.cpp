@@ -132,7 +132,7 @@ d4dgs_status d4dgs_workspace_size(int32_t n, int32_t width, int32_t height, int6
     if (!bytes) return fail(D4DGS_ERR_INVALID_ARG, "bytes is NULL");
     if (n < 0 || width <= 0 || height <= 0 || max_instances < 1 || max_instances > (int64_t)0x7fffffff)
         return fail(D4DGS_ERR_INVALID_ARG, "workspace sizes out of range");
-    *bytes = sort_workspace_bytes(n, max_instances);
+    *bytes = sort_workspace_bytes(n, max_instances, ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile));
     return D4DGS_OK;
 }
 
@@ -187,14 +187,14 @@ d4dgs_status d4dgs_bin_sort(const d4dgs_splats *splats, int32_t n, int32_t width
     if (width <= 0 || height <= 0 || width > 65535 * kTile || height > 65535 * kTile)
         return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
     if (!workspace) return fail(D4DGS_ERR_INVALID_ARG, "workspace is NULL");
-    if (workspace_bytes < sort_workspace_bytes(n, bins->capacity))
-        return fail(D4DGS_ERR_OUT_OF_MEMORY, "workspace smaller than d4dgs_workspace_size");
     d4dgs_camera dummy;
     std::memset(&dummy, 0, sizeof(dummy));
     dummy.width = width;
     dummy.height = height;
     const CamK ck = make_camk(dummy);
-    const SortWs ws = carve_workspace(workspace, n, bins->capacity);
+    if (workspace_bytes < sort_workspace_bytes(n, bins->capacity, ck.TX * ck.TY))
+        return fail(D4DGS_ERR_OUT_OF_MEMORY, "workspace smaller than d4dgs_workspace_size");
+    const SortWs ws = carve_workspace(workspace, n, bins->capacity, ck.TX * ck.TY);
     const hipError_t e = launch_bin_sort((const float4 *)splats->rec, splats->count, splats->offset, splats->partial,
                                          n, ck, ws, bins->keys, bins->values, bins->ranges, bins->num_instances,
                                          bins->capacity, d_status, (hipStream_t)stream);
@@ -205,7 +205,8 @@ d4dgs_status d4dgs_bin_sort_sync(const d4dgs_splats *splats, int32_t n, int32_t 
                                  void *workspace, size_t workspace_bytes, d4dgs_bins *bins, int64_t *num_instances,
                                  d4dgs_stream stream) {
     D4_TRY(d4dgs_bin_sort(splats, n, width, height, workspace, workspace_bytes, bins, nullptr, stream));
-    const SortWs ws = carve_workspace(workspace, n, bins->capacity);
+    const int tiles = ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+    const SortWs ws = carve_workspace(workspace, n, bins->capacity, tiles);
     int64_t total = 0;
     uint32_t misc[2] = {0, 0};
     hipError_t e = hipMemcpyAsync(&total, bins->num_instances, sizeof(total), hipMemcpyDeviceToHost, (hipStream_t)stream);

@@ -81,71 +81,92 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
         ig[3 * (size_t)slot + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
         ig[3 * (size_t)slot + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    for (uint32_t jj = nmax; jj-- > 0;) {
-        const uint32_t j = start + jj;
-        const uint32_t gi = vals[j];
-        const SplatK s = load_splat(rec, gi);
-        const float4 r0 = rec[3 * (size_t)gi + 0];
-        const float cA = r0.z, cB = r0.w, cC = rec[3 * (size_t)gi + 1].x;
-        float a_mx = 0.f, a_my = 0.f, a_A = 0.f, a_B = 0.f, a_C = 0.f, a_am = 0.f, a_r = 0.f, a_g = 0.f, a_b = 0.f;
-        bool any = false;
+    __shared__ float4 s0[kWave], s1[kWave], s2[kWave], s3[kWave];
+    // batches of 64 list entries, last batch first
+    for (uint32_t jb = start + nmax; jb > start;) {
+        const uint32_t j0 = jb - start > (uint32_t)kWave ? jb - kWave : start;
+        const uint32_t j = j0 + ln;
+        if (j < jb) {
+            const uint32_t gi = vals[j];
+            float4 f0, f1, f2;
+            fold_splat(rec, gi, f0, f1, f2);
+            s0[ln] = f0;
+            s1[ln] = f1;
+            s2[ln] = f2;
+            const float4 r0 = rec[3 * (size_t)gi + 0];
+            const float cC = rec[3 * (size_t)gi + 1].x;
+            s3[ln] = make_float4(r0.z, r0.w, cC, __uint_as_float(inst_slot(rec, offset, gi, tx, ty)));
+        }
+        __syncthreads();
+        for (int i = (int)(jb - j0) - 1; i >= 0; --i) {
+            const float4 f0 = s0[i], f1 = s1[i], f2 = s2[i], f3 = s3[i];
+            const uint32_t jj = j0 - start + (uint32_t)i;  // position in the tile's list
+            const float dx = sx - f0.x;
+            const ColTerms ct = col_terms(f0, f1, dx);
+            const float amax = f2.y;
+            const float cA = f3.x, cB = f3.y, cC = f3.z;
+            float a_mx = 0.f, a_my = 0.f, a_A = 0.f, a_B = 0.f, a_C = 0.f, a_am = 0.f, a_r = 0.f, a_g = 0.f,
+                  a_b = 0.f;
+            bool any = false;
 #pragma unroll
-        for (int k = 0; k < kPx; ++k) {
-            const float dx = sx - s.mx, dy = sy[k] - s.my;
-            const float q = splat_exponent(s, dx, dy);
-            const float G = exp2_fast(q);
-            const float araw = s.amax * G;
-            const float alpha = fminf(kAlphaMax, araw);
-            const bool ok = jj < nc[k] && q <= 0.0f && alpha >= kAlphaMin;
-            if (ok) {
-                any = true;
-                const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-                const float Ti = Tc[k] * inv;
-                const float da = g0[k] * (s.r * Ti - S0[k] * inv) + g1[k] * (s.g * Ti - S1[k] * inv) +
-                                 g2[k] * (s.b * Ti - S2[k] * inv);
-                const float wgt = alpha * Ti;
-                a_r += g0[k] * wgt;
-                a_g += g1[k] * wgt;
-                a_b += g2[k] * wgt;
-                S0[k] += s.r * wgt;
-                S1[k] += s.g * wgt;
-                S2[k] += s.b * wgt;
-                Tc[k] = Ti;
-                if (araw <= kAlphaMax) {
-                    const float dp = da * alpha;  // d/d(power), power the natural-log exponent
-                    a_am += da * G;
-                    a_mx += dp * (cA * dx + cB * dy);
-                    a_my += dp * (cC * dy + cB * dx);
-                    a_A += dp * (-0.5f * dx * dx);
-                    a_B += dp * (-(dx * dy));
-                    a_C += dp * (-0.5f * dy * dy);
+            for (int k = 0; k < kPx; ++k) {
+                const float dy = sy[k] - f0.y;
+                const float q = pix_exponent(ct, f1, dy);
+                const float e = exp2_fast(q);
+                const float alpha = fminf(kAlphaMax, e);
+                const bool ok = jj < nc[k] && !(q > f1.y) && alpha >= kAlphaMin;
+                if (ok) {
+                    any = true;
+                    const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                    const float Ti = Tc[k] * inv;  // transmittance in front of this splat
+                    const float da = g0[k] * (f1.z * Ti - S0[k] * inv) + g1[k] * (f1.w * Ti - S1[k] * inv) +
+                                     g2[k] * (f2.x * Ti - S2[k] * inv);
+                    const float wgt = alpha * Ti;
+                    a_r += g0[k] * wgt;
+                    a_g += g1[k] * wgt;
+                    a_b += g2[k] * wgt;
+                    S0[k] += f1.z * wgt;
+                    S1[k] += f1.w * wgt;
+                    S2[k] += f2.x * wgt;
+                    Tc[k] = Ti;
+                    if (e <= kAlphaMax) {  // not clamped: alpha = amax * exp(power)
+                        const float dp = da * alpha;  // d/d(power)
+                        a_am += da * (e * __builtin_amdgcn_rcpf(amax));
+                        a_mx += dp * (cA * dx + cB * dy);
+                        a_my += dp * (cC * dy + cB * dx);
+                        a_A += dp * (-0.5f * dx * dx);
+                        a_B += dp * (-(dx * dy));
+                        a_C += dp * (-0.5f * dy * dy);
+                    }
                 }
             }
-        }
-        const uint32_t slot = inst_slot(rec, offset, gi, tx, ty);
-        const bool slot_ok = slot < capacity;  // false only after an instance overflow
-        if (__ballot(any) == 0) {
-            if (ln == 0 && slot_ok) {
-                ig[3 * (size_t)slot + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
-                ig[3 * (size_t)slot + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-                ig[3 * (size_t)slot + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            const uint32_t slot = __float_as_uint(f3.w);
+            const bool slot_ok = slot < capacity;  // false only after an instance overflow
+            if (__ballot(any) == 0) {
+                if (ln == 0 && slot_ok) {
+                    ig[3 * (size_t)slot + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    ig[3 * (size_t)slot + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    ig[3 * (size_t)slot + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                continue;
             }
-            continue;
+            a_mx = wave_sum(a_mx);
+            a_my = wave_sum(a_my);
+            a_A = wave_sum(a_A);
+            a_B = wave_sum(a_B);
+            a_C = wave_sum(a_C);
+            a_am = wave_sum(a_am);
+            a_r = wave_sum(a_r);
+            a_g = wave_sum(a_g);
+            a_b = wave_sum(a_b);
+            if (ln == 0 && slot_ok) {
+                ig[3 * (size_t)slot + 0] = make_float4(a_mx, a_my, a_A, a_B);
+                ig[3 * (size_t)slot + 1] = make_float4(a_C, a_am, a_r, a_g);
+                ig[3 * (size_t)slot + 2] = make_float4(a_b, 0.f, 0.f, 0.f);
+            }
         }
-        a_mx = wave_sum(a_mx);
-        a_my = wave_sum(a_my);
-        a_A = wave_sum(a_A);
-        a_B = wave_sum(a_B);
-        a_C = wave_sum(a_C);
-        a_am = wave_sum(a_am);
-        a_r = wave_sum(a_r);
-        a_g = wave_sum(a_g);
-        a_b = wave_sum(a_b);
-        if (ln == 0 && slot_ok) {
-            ig[3 * (size_t)slot + 0] = make_float4(a_mx, a_my, a_A, a_B);
-            ig[3 * (size_t)slot + 1] = make_float4(a_C, a_am, a_r, a_g);
-            ig[3 * (size_t)slot + 2] = make_float4(a_b, 0.f, 0.f, 0.f);
-        }
+        __syncthreads();
+        jb = j0;
     }
 }
 

@@ -1,40 +1,44 @@
 // Per-tile front-to-back alpha blending (Eq. 4 with alpha_i = o_i w_i G'_i).
 //
-// One wavefront renders one 16x16 tile, four pixels per lane (lane l owns column l % 16
-// and rows l / 16 + 4k).  The wave walks the tile's depth-sorted list in order; the list
-// index, the Gaussian index and its 48-byte splat record are the same for every lane,
-// so they are loaded once per wave (scalar loads) and broadcast -- no LDS staging and no
-// block barriers.  The wave stops as soon as all of its pixels are saturated
-// (transmittance would drop below 1e-4), a wave-wide vote.
+// A 16x16 tile is rendered by 4 / PX wavefronts (one workgroup each), PX pixels per lane:
+// lane l owns column l % 16 and rows l / 16 + 4 k of its wave's band.  Each wavefront walks
+// the tile's depth-sorted list in batches of 64: every lane gathers one splat record,
+// folds it (exponent constants, log2 of the peak opacity) and parks it in LDS; then the
+// wave steps through the batch reading each splat as an LDS broadcast.  No block-wide
+// barriers (a workgroup is one wave).  The terms of the exponent that depend only on the
+// column are formed once per lane and shared by its pixels.  A wave stops as soon as all
+// of its pixels are saturated (wave-wide vote).
 //
 // Launch order is XCD-aware: the hardware deals consecutive workgroups round-robin to the
-// 8 XCDs, so block b renders tile (b % 8) * per_xcd + b / 8 -- each XCD gets a contiguous
-// band of tiles, and neighbouring tiles, which share splats, share that XCD's L2.
+// 8 XCDs, so block b takes logical block (b % 8) * per_xcd + b / 8 -- each XCD renders a
+// contiguous band of tiles, and neighbouring tiles, which share splats, share its L2.
 #include "internal.hpp"
 
 namespace d4 {
 
 namespace {
 
-constexpr int kPx = 4;  // pixels per lane
-
+template <int PX, bool STATE>
 __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                  const uint32_t *__restrict__ ranges, CamK c, float bg0, float bg1,
                                                  float bg2, float *__restrict__ img, float *__restrict__ final_T,
-                                                 uint32_t *__restrict__ ncontrib, int ntiles, int per_xcd) {
+                                                 uint32_t *__restrict__ ncontrib, int nlogical, int per_xcd) {
+    constexpr int WPT = 4 / PX;  // waves per tile
+    __shared__ float4 s0[kWave], s1[kWave], s2[kWave];
     const int b = blockIdx.x;
-    const int tile = (b & 7) * per_xcd + (b >> 3);
-    if (tile >= ntiles) return;
+    const int L = (b & 7) * per_xcd + (b >> 3);
+    if (L >= nlogical) return;
+    const int tile = L / WPT, sub = L % WPT;
     const int tx = tile % c.TX, ty = tile / c.TX;
     const int ln = lane_id();
     const int px = tx * kTile + (ln & 15);
-    float sx = (float)px + 0.5f, sy[kPx];
-    bool in[kPx], done[kPx];
-    float T[kPx], C0[kPx], C1[kPx], C2[kPx];
-    uint32_t last[kPx];
+    const float sx = (float)px + 0.5f;
+    float sy[PX], T[PX], C0[PX], C1[PX], C2[PX];
+    bool in[PX], done[PX];
+    uint32_t last[PX];
 #pragma unroll
-    for (int k = 0; k < kPx; ++k) {
-        const int py = ty * kTile + (ln >> 4) + 4 * k;
+    for (int k = 0; k < PX; ++k) {
+        const int py = ty * kTile + (ln >> 4) + 4 * (sub * PX + k);
         sy[k] = (float)py + 0.5f;
         in[k] = px < c.W && py < c.H;
         done[k] = !in[k];
@@ -43,52 +47,96 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
         last[k] = 0u;
     }
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-    for (uint32_t j = start; j < end; ++j) {
-        const bool alldone = done[0] && done[1] && done[2] && done[3];
-        if (__all(alldone)) break;
-        const uint32_t gi = vals[j];
-        const SplatK s = load_splat(rec, gi);
+    for (uint32_t j0 = start; j0 < end; j0 += kWave) {
+        bool lane_done = true;
 #pragma unroll
-        for (int k = 0; k < kPx; ++k) {
-            const float dx = sx - s.mx, dy = sy[k] - s.my;
-            const float q = splat_exponent(s, dx, dy);
-            const float alpha = fminf(kAlphaMax, s.amax * exp2_fast(q));
-            const bool ok = !done[k] && q <= 0.0f && alpha >= kAlphaMin;
-            const float Tn = T[k] * (1.0f - alpha);
-            const bool stop = ok && Tn < kTMin;
-            const bool blend = ok && !stop;
-            const float wgt = blend ? alpha * T[k] : 0.0f;
-            C0[k] = __builtin_fmaf(s.r, wgt, C0[k]);
-            C1[k] = __builtin_fmaf(s.g, wgt, C1[k]);
-            C2[k] = __builtin_fmaf(s.b, wgt, C2[k]);
-            T[k] = blend ? Tn : T[k];
-            last[k] = blend ? (j - start + 1) : last[k];
-            done[k] = done[k] || stop;
+        for (int k = 0; k < PX; ++k) lane_done = lane_done && done[k];
+        if (__all(lane_done)) break;
+        const uint32_t j = j0 + ln;
+        if (j < end) {
+            float4 f0, f1, f2;
+            fold_splat(rec, vals[j], f0, f1, f2);
+            s0[ln] = f0;
+            s1[ln] = f1;
+            s2[ln] = f2;
         }
+        __syncthreads();
+        const uint32_t nb = min((uint32_t)kWave, end - j0);
+        for (uint32_t i = 0; i < nb; ++i) {
+            const float4 f0 = s0[i], f1 = s1[i], f2 = s2[i];
+            const ColTerms ct = col_terms(f0, f1, sx - f0.x);
+            bool all_done = true;
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const float q = pix_exponent(ct, f1, sy[k] - f0.y);
+                const float alpha = fminf(kAlphaMax, exp2_fast(q));
+                const bool ok = !done[k] && !(q > f1.y) && alpha >= kAlphaMin;
+                const float Tn = T[k] * (1.0f - alpha);
+                const bool stop = ok && Tn < kTMin;
+                const bool blend = ok && !stop;
+                const float wgt = blend ? alpha * T[k] : 0.0f;
+                C0[k] = __builtin_fmaf(f1.z, wgt, C0[k]);
+                C1[k] = __builtin_fmaf(f1.w, wgt, C1[k]);
+                C2[k] = __builtin_fmaf(f2.x, wgt, C2[k]);
+                T[k] = blend ? Tn : T[k];
+                if (STATE) last[k] = blend ? (j0 - start + i + 1) : last[k];
+                done[k] = done[k] || stop;
+                all_done = all_done && done[k];
+            }
+            if (__all(all_done)) break;
+        }
+        __syncthreads();
     }
     const size_t plane = (size_t)c.W * c.H;
 #pragma unroll
-    for (int k = 0; k < kPx; ++k) {
+    for (int k = 0; k < PX; ++k) {
         if (!in[k]) continue;
-        const int py = ty * kTile + (ln >> 4) + 4 * k;
+        const int py = ty * kTile + (ln >> 4) + 4 * (sub * PX + k);
         const size_t pi = (size_t)py * c.W + px;
         img[pi] = C0[k] + T[k] * bg0;
         img[plane + pi] = C1[k] + T[k] * bg1;
         img[2 * plane + pi] = C2[k] + T[k] * bg2;
-        if (final_T) final_T[pi] = T[k];
-        if (ncontrib) ncontrib[pi] = last[k];
+        if (STATE) {
+            final_T[pi] = T[k];
+            ncontrib[pi] = last[k];
+        }
     }
+}
+
+template <int PX>
+void launch_px(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c, const float bg[3],
+               float *img, float *final_T, uint32_t *n_contrib, hipStream_t st) {
+    const int nlogical = c.TX * c.TY * (4 / PX);
+    const int per_xcd = (nlogical + 7) / 8;
+    if (final_T)
+        hipLaunchKernelGGL((k_blend<PX, true>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c, bg[0],
+                           bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd);
+    else
+        hipLaunchKernelGGL((k_blend<PX, false>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c, bg[0],
+                           bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd);
+}
+
+// Pixels per lane of the forward blend: 2 (measured best at 1352x1014); D4DGS_BLEND_PX
+// selects 4 or 1.
+int blend_px() {
+    static const int px = [] {
+        const char *e = getenv("D4DGS_BLEND_PX");
+        const int v = e ? atoi(e) : 2;
+        return (v == 1 || v == 2 || v == 4) ? v : 2;
+    }();
+    return px;
 }
 
 }  // namespace
 
 hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c,
                         const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st) {
-    const int ntiles = c.TX * c.TY;
-    if (ntiles == 0) return hipSuccess;
-    const int per_xcd = (ntiles + 7) / 8;
-    hipLaunchKernelGGL(k_blend, dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c, bg[0], bg[1], bg[2],
-                       img, final_T, n_contrib, ntiles, per_xcd);
+    if (c.TX * c.TY == 0) return hipSuccess;
+    switch (blend_px()) {
+        case 1: launch_px<1>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
+        case 2: launch_px<2>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
+        default: launch_px<4>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
+    }
     return hipGetLastError();
 }
 

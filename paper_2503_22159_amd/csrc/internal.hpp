@@ -13,12 +13,7 @@ namespace d4 {
 constexpr int kWave = 64;
 constexpr int kTile = D4DGS_TILE;
 constexpr int kBlock = 256;             // threads per block of the per-Gaussian kernels
-constexpr int kRadixBits = 8;           // LSD digit width
-constexpr int kRadix = 1 << kRadixBits; // buckets per pass
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;                         // keys per thread per chunk
-constexpr int kSortChunk = kSortThreads * kSortItems;  // keys per chunk (4096)
-constexpr int kSortGrid = 1024;  // blocks of the chunk-looping sort kernels
+constexpr int kRadix = 256;             // buckets of the 8-bit radix digits
 
 // fp32(2 ln 255): a Gaussian with tau^2 > kTemporalCull * s_t^2 has w < 1/255 and is culled.
 constexpr float kTemporalCull = 11.0825272f;
@@ -68,35 +63,45 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
-// The blend's per-(pixel, splat) opacity, shared bit-for-bit by forward and backward.
-// Folded exponent: q = log2(e) * (-1/2 (a dx^2 + c dy^2) - b dx dy) computed as
-// (qa dx + qb dy) dx + qc dy dy with qa = -log2(e)/2 a, qb = -log2(e) b, qc = -log2(e)/2 c.
-struct SplatK {
-    float mx, my, qa, qb, qc, amax, r, g, b;
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_logf(x); }
+
+// The blend's per-(pixel, splat) opacity, shared instruction for instruction by the
+// forward and the backward so that both take the same skip/stop decisions.
+//
+// Folded splat (3 x float4, staged in LDS):
+//   f0 = {m.x, m.y, qa, qb},  f1 = {qc, la, r, g},  f2 = {b, amax, -, -}
+// with qa = -log2(e)/2 a, qb = -log2(e) b, qc = -log2(e)/2 c (conic a, b, c) and
+// la = log2(amax), so that for d = sample - m
+//   q = qa dx^2 + qb dx dy + qc dy^2 + la = log2(amax) + log2(e) * power,
+//   alpha = min(0.99, 2^q),  and "power > 0" is "q > la".
+// Per lane the terms that depend only on dx are formed once and shared by the lane's
+// pixels, which lie in one column:  A0 = qa dx dx + la,  B0 = qb dx,
+//   q = (qc dy + B0) dy + A0.
+__device__ __forceinline__ void fold_splat(const float4 *__restrict__ rec, uint32_t gi, float4 &f0, float4 &f1,
+                                           float4 &f2) {
+    const float4 p = rec[3 * (size_t)gi + 0];
+    const float4 q = rec[3 * (size_t)gi + 1];
+    const float4 s = rec[3 * (size_t)gi + 2];
+    f0 = make_float4(p.x, p.y, (-0.5f * kLog2e) * p.z, (-kLog2e) * p.w);
+    f1 = make_float4((-0.5f * kLog2e) * q.x, log2_fast(q.y), q.z, q.w);
+    f2 = make_float4(s.x, q.y, 0.0f, 0.0f);
+}
+
+struct ColTerms {
+    float A0, B0;
 };
 
-__device__ __forceinline__ SplatK load_splat(const float4 *__restrict__ rec, uint32_t gi) {
-    const float4 p = rec[3 * gi + 0];
-    const float4 q = rec[3 * gi + 1];
-    const float4 s = rec[3 * gi + 2];
-    SplatK k;
-    k.mx = p.x;
-    k.my = p.y;
-    k.qa = (-0.5f * kLog2e) * p.z;
-    k.qb = (-kLog2e) * p.w;
-    k.qc = (-0.5f * kLog2e) * q.x;
-    k.amax = q.y;
-    k.r = q.z;
-    k.g = q.w;
-    k.b = s.x;
-    return k;
+__device__ __forceinline__ ColTerms col_terms(const float4 &f0, const float4 &f1, float dx) {
+    ColTerms t;
+    t.A0 = __builtin_fmaf(f0.z * dx, dx, f1.y);
+    t.B0 = f0.w * dx;
+    return t;
 }
 
-__device__ __forceinline__ float splat_exponent(const SplatK &k, float dx, float dy) {
-    return __builtin_fmaf(__builtin_fmaf(k.qa, dx, k.qb * dy), dx, (k.qc * dy) * dy);
+__device__ __forceinline__ float pix_exponent(const ColTerms &t, const float4 &f1, float dy) {
+    return __builtin_fmaf(__builtin_fmaf(f1.x, dy, t.B0), dy, t.A0);
 }
-
-__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // --- launchers (host side) ----------------------------------------------------------
 struct SceneK {
@@ -111,17 +116,14 @@ hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, flo
                           float4 *rec, uint32_t *count, uint32_t *block_sums, hipStream_t st);
 
 struct SortWs {
-    uint32_t *block_sums;  // unused (the per-block sums live in d4dgs_splats::partial)
-    uint64_t *alt_keys;    // capacity
-    uint32_t *alt_vals;    // capacity
-    uint32_t *hist;        // kRadix * max_chunks
-    uint32_t *misc;        // small scalars
-    int64_t max_chunks;
+    uint64_t *bucket;  // [capacity] per-tile buckets of (depth bits << 32 | gaussian)
+    uint64_t *alt;     // [capacity] scratch of the large-bucket radix sort
+    uint32_t *tcnt;    // [tiles] tile counters, then bucket cursors
+    uint32_t *misc;    // [64]: [0] instances kept, [1] status
 };
 
-size_t sort_workspace_bytes(int n, int64_t capacity);
-SortWs carve_workspace(void *ws, int n, int64_t capacity);
-int sort_passes(int tiles);
+size_t sort_workspace_bytes(int n, int64_t capacity, int tiles);
+SortWs carve_workspace(void *ws, int n, int64_t capacity, int tiles);
 
 hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *offset, uint32_t *partial, int n,
                            const CamK &c, const SortWs &ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
