@@ -3,13 +3,14 @@
 Workload (the frames/s headline): 300,000 Gaussians (32-cluster mixture, SH degree 3)
 rendered at 1352x1014 from 20 cameras on a 120-degree arc of radius 10, each at 300
 evenly spaced times -- a camera-major sweep with the camera-stage cache on (the camera
-stage runs once per camera, the time stage, binning, sort and blend once per frame).
+stage runs once per camera; the time stage, binning, sort and blend once per frame).
 One step = one camera's 300 frames.  Inputs are synthetic and resident in HBM before
 timing starts.
 
-Printed: one JSON line with frames/s, the roofline of the dominant kernel, the CPU
-oracle timed on a bounded sample, and side measurements (forward + backward step time
-at the same scene and resolution; serving latency).
+Printed: one JSON line with frames/s, the roofline of the dominant kernel (the blend,
+timed with HIP events on the stream it runs on), the CPU oracle timed on a bounded
+sample of the same frames, and side measurements: forward + backward at the same scene
+and resolution, and serving latency.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 2]
 """
@@ -25,8 +26,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
 FRAMES_PER_STEP = 300
+# Blend roofline.  Algorithmic work per (pixel, splat) evaluation of Eq. 4, counted on
+# the definition: exponent -1/2(a dx^2 + c dy^2) - b dx dy (11 flops), exp (1),
+# alpha = amax G (1), T' = T (1 - alpha) (2), C += c alpha T (7)  ->  22 flops.
+FLOPS_PER_EVAL = 22
+# FP32 vector peak without packed math: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -38,8 +44,93 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-frames", type=int, default=10)
+    ap.add_argument("--bwd-frames", type=int, default=20)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     return ap.parse_args()
+
+
+def sweep(args, ds, cams, times, render):
+    """The timed camera-major sweep; HIP events bracket every blend launch."""
+    import torch
+
+    W, H = cams[0].width, cams[0].height
+    rend = render.Renderer(ds, W, H, capacity=4 * ds.n, cache=True)
+    events = []
+
+    def step(k, record):
+        cam = cams[k % len(cams)]
+        for t in times:
+            render.project(ds, cam, t, rend.st, rend.cache)
+            render.bin_sort(rend.st)
+            if record:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                rend.blend()
+                e1.record()
+                events.append((e0, e1))
+            else:
+                rend.blend()
+
+    for k in range(args.warmup):
+        step(len(cams) - 1 - k, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k, True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert not rend.overflowed(), "instance capacity exceeded during the sweep"
+    blend_ms = [a.elapsed_time(b) for a, b in events]
+    return elapsed, sum(blend_ms) / len(blend_ms)
+
+
+def fwd_bwd(args, ds, cams, render, inputs):
+    """Forward + backward at the same scene and resolution (training-style: no camera
+    cache, parameters may change between steps)."""
+    import numpy as np
+    import torch
+
+    W, H = cams[0].width, cams[0].height
+    rend = render.Renderer(ds, W, H, capacity=4 * ds.n, cache=False, keep_state=True)
+    grads = render.grads_like(ds)
+    dL = torch.from_numpy(inputs.upstream_grad(7, W, H)).cuda()
+    views = [(cams[(3 * i) % len(cams)], np.float32((i % 10) / 9.0)) for i in range(args.bwd_frames)]
+    for cam, t in views[:2]:
+        rend.render(cam, t)
+        rend.backward(cam, t, dL, grads)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for cam, t in views:
+        rend.render(cam, t)
+        rend.backward(cam, t, dL, grads)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    assert not rend.overflowed()
+    return {"frames_per_s": round(len(views) / el, 2), "ms_per_frame": round(1000 * el / len(views), 4),
+            "frames": len(views), "camera_cache": False}
+
+
+def cpu_baseline(args, scene, cams, times):
+    """The oracle (plain C + OpenMP, FP32 decisions / FP64 blend) on a bounded sample of
+    the timed frames; also returns the oracle's count of blend evaluations."""
+    import oracle
+
+    oracle.build(force=False)
+    n = args.cpu_frames
+    idx = [(j * len(cams)) // n for j in range(n)]
+    sample = [(cams[j], times[(j * 37) % len(times)]) for j in idx]
+    evals = []
+    t0 = time.perf_counter()
+    for cam, t in sample:
+        _, _, res = oracle.render(scene, cam, t)
+        evals.append(res["n_eval"])
+    el = time.perf_counter() - t0
+    base = {"value": round(n / el, 4), "unit": "frames/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} frames of the timed sweep (cameras {idx[0]}..{idx[-1]} step {idx[1] - idx[0]}, "
+                      f"t spread over [0,1]); project + bin + blend per frame"}
+    return base, sum(evals) / len(evals)
 
 
 def main():
@@ -60,27 +151,12 @@ def main():
     cams = inputs.config2_cameras()
     times = [np.float32(k / (args.frames - 1)) for k in range(args.frames)]
     W, H = cams[0].width, cams[0].height
-    rend = render.Renderer(ds, W, H, capacity=4 * scene.n, cache=True)
 
-    def step(k):
-        cam = cams[k % len(cams)]
-        for t in times:
-            rend.render(cam, t)
-
-    for k in range(args.warmup):
-        step(len(cams) - 1 - k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(k)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    assert not rend.overflowed(), "instance capacity exceeded during the sweep"
+    elapsed, blend_ms = sweep(args, ds, cams, times, render)
     frames = args.steps * args.frames
-    fps = frames / elapsed
     out = {
         "metric": "frames/sec @1352x1014, 300k Gaussians fwd/bwd; serving p50/p99 ms vs plain",
-        "value": round(fps, 2),
+        "value": round(frames / elapsed, 2),
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -94,7 +170,25 @@ def main():
         "config": {"workload": "300k Gaussians (SH3, 32 clusters), 1352x1014, 20-camera arc x 300 times, "
                                "camera-stage cache on", "frames_per_step": args.frames,
                    "gaussians": scene.n, "width": W, "height": H},
+        "blend_ms_avg": round(blend_ms, 5),
     }
+    if not args.no_bwd:
+        out["fwd_bwd"] = fwd_bwd(args, ds, cams, render, inputs)
+    if not args.no_serve:
+        try:
+            from paper_2503_22159_amd import serve_bench
+
+            out["serving"] = serve_bench.run(seconds=args.serve_seconds)
+        except ImportError:
+            out["serving"] = None
+    if not args.no_cpu:
+        base, mean_evals = cpu_baseline(args, scene, cams, times)
+        out["cpu_baseline"] = base
+        achieved = mean_evals * FLOPS_PER_EVAL / (blend_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": "k_blend", "achieved": round(achieved, 3),
+                           "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                           "traffic": None, "evals_per_frame": int(mean_evals),
+                           "flops_per_eval": FLOPS_PER_EVAL}
     print(json.dumps(out), flush=True)
 
 

@@ -223,6 +223,7 @@ typedef struct {
     float bg[3];
     int64_t max_instances_per_pixel_x1000; /* instance capacity per request =
                                               width * height * this / 1000 (e.g. 1000) */
+    int32_t max_queue;            /* requests waiting for admission; 0 = 4 * max_inflight */
 } d4dgs_serve_config;
 
 typedef struct {
@@ -245,7 +246,7 @@ typedef struct d4dgs_server d4dgs_server;
 d4dgs_status d4dgs_serve_create(const d4dgs_scene *scene, const d4dgs_serve_config *cfg,
                                 d4dgs_server **out);
 /* Queue a request; never blocks.  out_img (device) [3][height][width] is written
- * before the request is reported done.  BUSY when the queue holds 4 * max_inflight. */
+ * before the request is reported done.  BUSY when max_queue requests already wait. */
 d4dgs_status d4dgs_serve_submit(d4dgs_server *s, const d4dgs_camera *cam, float t, float *out_img,
                                 uint64_t *ticket);
 /* *done = 1 once the image is complete (stats filled, the ticket is then released). */

@@ -89,6 +89,7 @@ def lib():
         L.oc_sh_basis.restype = None
         L.oc_set_threads.argtypes = [C.c_int]
         L.oc_set_threads.restype = None
+        L.oc_num_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -96,6 +97,10 @@ def lib():
 def set_threads(n):
     """OpenMP threads of the oracle (0 = all processors)."""
     lib().oc_set_threads(int(n))
+
+
+def num_threads():
+    return int(lib().oc_num_threads())
 
 
 def _p(a):

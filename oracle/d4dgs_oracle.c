@@ -104,6 +104,8 @@ __attribute__((constructor)) static void sh_tables_init(void)
 /* Thread count of the OpenMP regions (0 = the OpenMP default). */
 void oc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
 
+int oc_num_threads(void) { return omp_get_max_threads(); }
+
 /* ---------------- three instantiations of the body ---------------- */
 #define REAL float
 #define DEC float

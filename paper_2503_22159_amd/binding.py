@@ -60,7 +60,8 @@ class Grads(C.Structure):
 
 class ServeConfig(C.Structure):
     _fields_ = [("max_inflight", C.c_int32), ("max_batch", C.c_int32), ("scratch_budget_bytes", C.c_int64),
-                ("n_streams", C.c_int32), ("bg", C.c_float * 3), ("max_instances_per_pixel_x1000", C.c_int64)]
+                ("n_streams", C.c_int32), ("bg", C.c_float * 3), ("max_instances_per_pixel_x1000", C.c_int64),
+                ("max_queue", C.c_int32)]
 
 
 class ReqStats(C.Structure):

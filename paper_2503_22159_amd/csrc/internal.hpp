@@ -115,6 +115,21 @@ SceneK make_scenek(const d4dgs_scene &s);
 hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, float *cam_rec, int cam_cap,
                           float4 *rec, uint32_t *count, uint32_t *block_sums, hipStream_t st);
 
+// One request of a batched projection (kernel argument, by value).
+struct ReqK {
+    CamK cam;
+    float t;
+    float4 *rec;
+    uint32_t *count;
+    uint32_t *partial;
+};
+constexpr int kMaxBatch = 16;  // requests per batched-projection launch
+struct BatchArgs {
+    int nreq;
+    ReqK r[kMaxBatch];
+};
+hipError_t launch_project_batch(const SceneK &s, const BatchArgs &args, hipStream_t st);
+
 struct SortWs {
     uint64_t *bucket;  // [capacity] per-tile buckets of (depth bits << 32 | gaussian)
     uint64_t *alt;     // [capacity] scratch of the large-bucket radix sort

@@ -1,8 +1,10 @@
 // Projection of disentangled 4D Gaussians into dynamic 2D Gaussians (Alg. 1; Eq. 9-15).
 //
-// Camera stage (runs when the camera changes): covariance from scale and quaternion,
-// camera-space mean (Eq. 9-10) and velocity (Eq. 11), pixel-space mean and its
-// first-order velocity (Eq. 12-13), W Sigma W^T, and the view-dependent colour.
+// Camera stage (runs when the camera changes): camera-space mean (Eq. 9-10) and
+// velocity (Eq. 11), pixel-space mean and its first-order velocity (Eq. 12-13),
+// W Sigma W^T, and the view-dependent colour.  Sigma = (Rq S)(Rq S)^T depends on the
+// Gaussian only and is formed once per Gaussian, also when one launch projects a batch
+// of cameras (the server's batched projection reads each Gaussian's parameters once).
 // Time stage (runs every frame): temporal weight of the conditional slice, the moved
 // mean, the Jacobian at the moved camera-space mean (Eq. 14), Sigma' (Eq. 15), conic,
 // screen extent and tile rectangle.  No 4D slicing and no 4x4 work.
@@ -21,12 +23,63 @@ struct CamRec {
     float p[3], u[3], cv[6], m0[2], md[2], rgb[3];
 };
 
+// Parameters of one Gaussian and its camera-independent covariance.
+template <int DEG>
+struct GParams {
+    static constexpr int K = (DEG + 1) * (DEG + 1);
+    bool ok;  // false for a zero quaternion
+    float S[9];
+    float mu[3], v[3];
+    float sh[3 * K];  // [k][rgb]
+};
+
+template <int DEG>
+__device__ __forceinline__ void load_params(const SceneK &s, int gi, GParams<DEG> &P) {
+    const int n = s.n;
+    const float q0 = s.quat[gi], q1 = s.quat[n + gi], q2 = s.quat[2 * n + gi], q3 = s.quat[3 * n + gi];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        P.mu[i] = s.mean[i * n + gi];
+        P.v[i] = s.velocity[i * n + gi];
+    }
+#pragma unroll
+    for (int k = 0; k < 3 * GParams<DEG>::K; ++k) P.sh[k] = s.sh[(size_t)k * n + gi];
+    const float n2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
+    P.ok = n2 > 0.0f;
+    if (!P.ok) return;
+    const float nrm = sqrtf(n2);
+    const float qw = q0 / nrm, qx = q1 / nrm, qy = q2 / nrm, qz = q3 / nrm;
+    float Rq[9];
+    Rq[0] = 1.0f - 2.0f * (qy * qy + qz * qz);
+    Rq[1] = 2.0f * (qx * qy - qw * qz);
+    Rq[2] = 2.0f * (qx * qz + qw * qy);
+    Rq[3] = 2.0f * (qx * qy + qw * qz);
+    Rq[4] = 1.0f - 2.0f * (qx * qx + qz * qz);
+    Rq[5] = 2.0f * (qy * qz - qw * qx);
+    Rq[6] = 2.0f * (qx * qz - qw * qy);
+    Rq[7] = 2.0f * (qy * qz + qw * qx);
+    Rq[8] = 1.0f - 2.0f * (qx * qx + qy * qy);
+    const float sx = s.scale[gi], sy = s.scale[n + gi], sz = s.scale[2 * n + gi];
+    float M[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        M[3 * i + 0] = Rq[3 * i + 0] * sx;
+        M[3 * i + 1] = Rq[3 * i + 1] * sy;
+        M[3 * i + 2] = Rq[3 * i + 2] * sz;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            P.S[3 * i + j] =
+                (M[3 * i + 0] * M[3 * j + 0] + M[3 * i + 1] * M[3 * j + 1]) + M[3 * i + 2] * M[3 * j + 2];
+}
+
 // Real spherical harmonics (Condon-Shortley phase), degrees 0..3, as polynomials in
 // the unit direction; constants are the normalisations sqrt((2l+1)/4pi (l-m)!/(l+m)!)
 // (times sqrt 2 for m != 0).
 template <int DEG>
-__device__ __forceinline__ void sh_colour(int n, int gi, const float *__restrict__ sh, float x, float y, float z,
-                                          float rgb[3]) {
+__device__ __forceinline__ void sh_colour(const float *sh, float x, float y, float z, float rgb[3]) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     float Y[16];
     Y[0] = 0.28209479177387814f;
@@ -56,59 +109,28 @@ __device__ __forceinline__ void sh_colour(int n, int gi, const float *__restrict
     for (int c = 0; c < 3; ++c) {
         float acc = 0.0f;
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc = __builtin_fmaf(Y[k], sh[(size_t)(k * 3 + c) * n + gi], acc);
+        for (int k = 0; k < K; ++k) acc = __builtin_fmaf(Y[k], sh[k * 3 + c], acc);
         acc = acc + 0.5f;
         rgb[c] = acc < 0.0f ? 0.0f : acc;
     }
 }
 
-// Camera stage for Gaussian gi.  Returns false for a zero quaternion.
+// Camera stage (the camera-dependent part).  Requires P.ok.
 template <int DEG>
-__device__ __forceinline__ bool camera_stage(const SceneK &s, const CamK &c, int gi, CamRec &o) {
-    const int n = s.n;
-    const float q0 = s.quat[gi], q1 = s.quat[n + gi], q2 = s.quat[2 * n + gi], q3 = s.quat[3 * n + gi];
-    const float n2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
-    if (!(n2 > 0.0f)) return false;
-    const float nrm = sqrtf(n2);
-    const float qw = q0 / nrm, qx = q1 / nrm, qy = q2 / nrm, qz = q3 / nrm;
-    float Rq[9];
-    Rq[0] = 1.0f - 2.0f * (qy * qy + qz * qz);
-    Rq[1] = 2.0f * (qx * qy - qw * qz);
-    Rq[2] = 2.0f * (qx * qz + qw * qy);
-    Rq[3] = 2.0f * (qx * qy + qw * qz);
-    Rq[4] = 1.0f - 2.0f * (qx * qx + qz * qz);
-    Rq[5] = 2.0f * (qy * qz - qw * qx);
-    Rq[6] = 2.0f * (qx * qz - qw * qy);
-    Rq[7] = 2.0f * (qy * qz + qw * qx);
-    Rq[8] = 1.0f - 2.0f * (qx * qx + qy * qy);
-    const float sx = s.scale[gi], sy = s.scale[n + gi], sz = s.scale[2 * n + gi];
-    float M[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        M[3 * i + 0] = Rq[3 * i + 0] * sx;
-        M[3 * i + 1] = Rq[3 * i + 1] * sy;
-        M[3 * i + 2] = Rq[3 * i + 2] * sz;
-    }
-    float S[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            S[3 * i + j] = (M[3 * i + 0] * M[3 * j + 0] + M[3 * i + 1] * M[3 * j + 1]) + M[3 * i + 2] * M[3 * j + 2];
-    const float mx = s.mean[gi], my = s.mean[n + gi], mz = s.mean[2 * n + gi];
-    const float vx = s.velocity[gi], vy = s.velocity[n + gi], vz = s.velocity[2 * n + gi];
+__device__ __forceinline__ void camera_stage(const GParams<DEG> &P, const CamK &c, CamRec &o) {
     const float *R = c.R;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        o.p[i] = ((R[3 * i + 0] * mx + R[3 * i + 1] * my) + R[3 * i + 2] * mz) + c.T[i];
-        o.u[i] = (R[3 * i + 0] * vx + R[3 * i + 1] * vy) + R[3 * i + 2] * vz;
+        o.p[i] = ((R[3 * i + 0] * P.mu[0] + R[3 * i + 1] * P.mu[1]) + R[3 * i + 2] * P.mu[2]) + c.T[i];
+        o.u[i] = (R[3 * i + 0] * P.v[0] + R[3 * i + 1] * P.v[1]) + R[3 * i + 2] * P.v[2];
     }
     float A[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            A[3 * i + j] = (R[3 * i + 0] * S[0 * 3 + j] + R[3 * i + 1] * S[1 * 3 + j]) + R[3 * i + 2] * S[2 * 3 + j];
+            A[3 * i + j] =
+                (R[3 * i + 0] * P.S[0 * 3 + j] + R[3 * i + 1] * P.S[1 * 3 + j]) + R[3 * i + 2] * P.S[2 * 3 + j];
     const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
@@ -120,10 +142,9 @@ __device__ __forceinline__ bool camera_stage(const SceneK &s, const CamK &c, int
     o.md[0] = (c.fx * o.u[0]) / o.p[2];
     o.md[1] = (c.fy * o.u[1]) / o.p[2];
     // colour from the direction camera centre -> static mean
-    const float dx = mx - c.campos[0], dy = my - c.campos[1], dz = mz - c.campos[2];
+    const float dx = P.mu[0] - c.campos[0], dy = P.mu[1] - c.campos[1], dz = P.mu[2] - c.campos[2];
     const float len = sqrtf((dx * dx + dy * dy) + dz * dz);
-    sh_colour<DEG>(n, gi, s.sh, dx / len, dy / len, dz / len, o.rgb);
-    return true;
+    sh_colour<DEG>(P.sh, dx / len, dy / len, dz / len, o.rgb);
 }
 
 // Time stage.  Returns the tile count (0 = culled) and fills the splat record.
@@ -188,6 +209,14 @@ __device__ __forceinline__ void block_count_sum(uint32_t cnt, uint32_t *block_su
         for (int w = 0; w < kBlock / kWave; ++w) s += part[w];
         block_sums[blockIdx.x] = s;
     }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void store_rec(float4 *__restrict__ rec, int gi, const float4 &r0, const float4 &r1,
+                                          const float4 &r2) {
+    rec[3 * (size_t)gi + 0] = r0;
+    rec[3 * (size_t)gi + 1] = r1;
+    rec[3 * (size_t)gi + 2] = r2;
 }
 
 // MODE 0: camera + time stage; 1: camera + time stage and store the camera record;
@@ -221,8 +250,12 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneK s, CamK c, float t, f
                 for (int i = 0; i < 3; ++i) cr.rgb[i] = cam_rec[(size_t)(16 + i) * cap + gi];
             }
         } else {
-            ok = camera_stage<DEG>(s, c, gi, cr);
-            if (!ok) {
+            GParams<DEG> P;
+            load_params<DEG>(s, gi, P);
+            ok = P.ok;
+            if (ok) {
+                camera_stage<DEG>(P, c, cr);
+            } else {
                 // a zero quaternion: mark the record so that the time stage culls it
 #pragma unroll
                 for (int i = 0; i < 3; ++i) cr.p[i] = 0.0f;
@@ -249,15 +282,44 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneK s, CamK c, float t, f
         if (ok) {
             float4 r0, r1, r2;
             cnt = time_stage(cr, s.opacity[gi], s.t_mean[gi], s.t_scale[gi], t, c, r0, r1, r2);
-            if (cnt) {
-                rec[3 * (size_t)gi + 0] = r0;
-                rec[3 * (size_t)gi + 1] = r1;
-                rec[3 * (size_t)gi + 2] = r2;
-            }
+            if (cnt) store_rec(rec, gi, r0, r1, r2);
         }
         count[gi] = cnt;
     }
     block_count_sum(cnt, block_sums);
+}
+
+// Batched projection for the server: one thread per Gaussian loads its parameters and
+// covariance once, then runs the camera and time stages for every request of the batch
+// (the same arithmetic as k_project<0>, so each request's record is bit-identical to a
+// single-request projection).
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_project_batch(SceneK s, BatchArgs args) {
+    const int gi = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = gi < s.n;
+    GParams<DEG> P;
+    float op = 0.f, mut = 0.f, st = 1.f;
+    if (valid) {
+        load_params<DEG>(s, gi, P);
+        op = s.opacity[gi];
+        mut = s.t_mean[gi];
+        st = s.t_scale[gi];
+    } else {
+        P.ok = false;
+    }
+    for (int r = 0; r < args.nreq; ++r) {
+        const ReqK &q = args.r[r];
+        uint32_t cnt = 0;
+        if (valid && P.ok) {
+            CamRec cr;
+            camera_stage<DEG>(P, q.cam, cr);
+            float4 r0, r1, r2;
+            cnt = time_stage(cr, op, mut, st, q.t, q.cam, r0, r1, r2);
+            if (cnt) store_rec(q.rec, gi, r0, r1, r2);
+        }
+        if (valid) q.count[gi] = cnt;
+        block_count_sum(cnt, q.partial);
+    }
 }
 
 }  // namespace
@@ -284,6 +346,18 @@ hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, flo
         }
     }
 #undef D4_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_project_batch(const SceneK &s, const BatchArgs &args, hipStream_t st) {
+    if (s.n == 0 || args.nreq == 0) return hipSuccess;
+    const int grid = (s.n + kBlock - 1) / kBlock;
+    switch (s.deg) {
+        case 0: hipLaunchKernelGGL(k_project_batch<0>, dim3(grid), dim3(kBlock), 0, st, s, args); break;
+        case 1: hipLaunchKernelGGL(k_project_batch<1>, dim3(grid), dim3(kBlock), 0, st, s, args); break;
+        case 2: hipLaunchKernelGGL(k_project_batch<2>, dim3(grid), dim3(kBlock), 0, st, s, args); break;
+        default: hipLaunchKernelGGL(k_project_batch<3>, dim3(grid), dim3(kBlock), 0, st, s, args); break;
+    }
     return hipGetLastError();
 }
 

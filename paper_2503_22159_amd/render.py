@@ -83,6 +83,7 @@ class FrameState:
         self.img = None
         self.final_T = None
         self.n_contrib = None
+        self.inst_grads = None
 
     def splats(self):
         s = B.Splats()
@@ -184,7 +185,8 @@ def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, gra
     if grads is None:
         grads = grads_like(scene)
     dL = dL_dimg.contiguous().float()
-    st.inst_grads = torch.empty(max(st.capacity, 1) * B.GRAD_FLOATS, dtype=torch.float32, device=dL.device)
+    if getattr(st, "inst_grads", None) is None:
+        st.inst_grads = torch.empty(max(st.capacity, 1) * B.GRAD_FLOATS, dtype=torch.float32, device=dL.device)
     g = B.Grads()
     for k in FIELDS:
         setattr(g, k, grads[k].data_ptr())
@@ -234,7 +236,27 @@ class Renderer:
         assert cam.width == self.width and cam.height == self.height
         project(self.scene, cam, t, self.st, self.cache)
         bin_sort(self.st)
-        return blend(self.st, bg, self.keep_state, img=self.img)
+        return self.blend(bg)
+
+    def blend(self, bg=(0.0, 0.0, 0.0)):
+        if self.keep_state and self.st.final_T is None:
+            dev = self.img.device
+            self.st.final_T = torch.empty((self.height, self.width), dtype=torch.float32, device=dev)
+            self.st.n_contrib = torch.empty((self.height, self.width), dtype=torch.int32, device=dev)
+        st = self.st
+        sp, bn = st.splats(), st.bins()
+        B.check(B.lib.d4dgs_render_fwd(C.byref(sp), C.byref(bn), self.width, self.height, C.byref(_bg(bg)),
+                                       _ptr(self.img), _ptr(st.final_T) if self.keep_state else None,
+                                       _ptr(st.n_contrib) if self.keep_state else None, _stream()))
+        return self.img
+
+    def backward(self, cam, t, dL_dimg, grads, bg=(0.0, 0.0, 0.0)):
+        """Adjoint of the last render() (needs keep_state=True); adds into grads."""
+        assert self.keep_state
+        if getattr(self.st, "inst_grads", None) is None:
+            self.st.inst_grads = torch.empty(self.st.capacity * B.GRAD_FLOATS, dtype=torch.float32,
+                                             device=self.img.device)
+        return render_backward(self.scene, cam, t, bg, self.st, dL_dimg, grads)
 
     def overflowed(self):
         """True if any frame since the last reset exceeded the instance capacity."""

@@ -1,0 +1,125 @@
+"""GPU tests of the continuous-batching server (d4dgs_serve_*)."""
+import numpy as np
+import pytest
+
+import oracle
+from _helpers import compare_images
+from paper_2503_22159_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2503_22159_amd import render, serve
+
+    sc = inputs.config4_scene(n=60_000)
+    ds = render.DeviceScene.from_inputs(sc)
+    return sc, ds, render, serve
+
+
+def small_requests(k, seed=7):
+    rng = np.random.default_rng(seed)
+    sizes = [(160, 120), (338, 254), (480, 270)]
+    out = []
+    for i in range(k):
+        w, h = sizes[rng.integers(3)]
+        out.append((inputs.sphere_camera(rng, 10.0, w, h), np.float32(rng.uniform(0, 1))))
+    return out
+
+
+def test_alone_equals_mix_bitwise(env):
+    """64 requests submitted at once (batched, overlapped on 4 streams) give bitwise the
+    images of the same requests rendered alone through the plain path."""
+    import torch
+
+    sc, ds, R, S = env
+    reqs = small_requests(64)
+    outs = [torch.full((3, c.height, c.width), float("nan"), device="cuda") for c, _ in reqs]
+    with S.Server(ds, max_inflight=64, max_batch=16, budget_bytes=2 << 30, n_streams=4) as srv:
+        tks = [srv.submit(c, t, o) for (c, t), o in zip(reqs, outs)]
+        stats = [srv.wait(tk) for tk in tks]
+        assert all(s["status"] == 0 for s in stats)
+        assert max(s["batch_size"] for s in stats) > 1, "requests were never batched"
+    torch.cuda.synchronize()
+    for (c, t), o in zip(reqs, outs):
+        alone, _ = R.render_forward(ds, c, t)
+        assert torch.equal(o, alone)
+
+
+def test_served_images_match_oracle(env):
+    import torch
+
+    sc, ds, R, S = env
+    reqs = small_requests(4, seed=3)
+    outs = [torch.empty((3, c.height, c.width), device="cuda") for c, _ in reqs]
+    with S.Server(ds, max_inflight=8, max_batch=4, budget_bytes=1 << 30, n_streams=2) as srv:
+        for tk in [srv.submit(c, t, o) for (c, t), o in zip(reqs, outs)]:
+            assert srv.wait(tk)["status"] == 0
+    for (c, t), o in zip(reqs, outs):
+        _, _, res = oracle.render(sc, c, t)
+        compare_images(o.cpu().numpy(), None, None, res)
+
+
+def test_capacity_overflow_is_retried(env):
+    import torch
+
+    sc, ds, R, S = env
+    c, t = inputs.look_at((0.0, 3.0, -9.5), width=1352, height=1014), np.float32(0.5)
+    o = torch.empty((3, c.height, c.width), device="cuda")
+    # 0.001 instances per pixel -> the 65536 minimum, below this view's instance count
+    with S.Server(ds, max_inflight=4, max_batch=4, budget_bytes=1 << 30, n_streams=1,
+                  instances_per_pixel=0.001) as srv:
+        st = srv.wait(srv.submit(c, t, o))
+        assert st["status"] == 0 and st["num_instances"] > 65536
+        assert srv.stats()["retried"] >= 1
+    alone, _ = R.render_forward(ds, c, t)
+    assert torch.equal(o, alone)
+
+
+def test_admission_respects_budget_and_rejects_oversized(env):
+    import torch
+
+    sc, ds, R, S = env
+    reqs = small_requests(12, seed=9)
+    outs = [torch.empty((3, c.height, c.width), device="cuda") for c, _ in reqs]
+    budget = 24 << 20  # room for only a couple of requests at a time
+    with S.Server(ds, max_inflight=64, max_batch=16, budget_bytes=budget, n_streams=2) as srv:
+        tks = [srv.submit(c, t, o) for (c, t), o in zip(reqs, outs)]
+        sts = [srv.wait(tk) for tk in tks]
+        assert all(s["status"] == 0 for s in sts)
+        st = srv.stats()
+        assert 0 < st["arena_peak_bytes"] <= budget
+        big = inputs.look_at((0, 0, -10.0), width=1920, height=1080)
+        ob = torch.empty((3, 1080, 1920), device="cuda")
+        from paper_2503_22159_amd import binding as B
+
+        assert srv.wait(srv.submit(big, 0.5, ob))["status"] == B.ERR_OUT_OF_MEMORY
+    for (c, t), o in zip(reqs, outs):
+        alone, _ = R.render_forward(ds, c, t)
+        assert torch.equal(o, alone)
+
+
+def test_destroy_with_queued_requests(env):
+    import torch
+
+    from paper_2503_22159_amd import binding as B
+
+    sc, ds, R, S = env
+    reqs = small_requests(20, seed=11)
+    outs = [torch.empty((3, c.height, c.width), device="cuda") for c, _ in reqs]
+    srv = S.Server(ds, max_inflight=1, max_batch=1, budget_bytes=1 << 30, n_streams=1)
+    accepted = busy = 0
+    for (c, t), o in zip(reqs, outs):
+        try:
+            srv.submit(c, t, o)
+            accepted += 1
+        except B.D4Error as e:  # the queue holds 4 x max_inflight requests
+            assert e.status == B.ERR_BUSY
+            busy += 1
+    assert accepted >= 4 and accepted + busy == len(reqs)
+    srv.close()  # cancels what was not admitted, drains what was
+    torch.cuda.synchronize()
