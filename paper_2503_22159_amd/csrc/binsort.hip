@@ -86,33 +86,82 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t *__rest
     }
 }
 
-template <bool COUNT>
+// Emission of tile instances, in two passes over each block of 256 Gaussians.
+//
+// RESERVE: per-Gaussian offsets (block scan), then every instance gets a position inside
+//   its tile's bucket, relative to the bucket start.  Device-scope atomics are expensive
+//   on this part, so they are aggregated: when the block's splats together cover at most
+//   kCells tiles (a spatially coherent block), instances are counted in LDS and one
+//   global atomic per (block, tile) reserves the group's range (stored in grp_off);
+//   otherwise each instance reserves its own slot (stored in inst_off, indexed by its
+//   emission position).
+// SCATTER (after the tile scan): recomputes the same enumeration, takes a rank inside its
+//   group from an LDS counter (any unique rank will do -- the per-tile sort fixes the
+//   final order) and writes its key to bucket[tile start + reserved offset].  No global
+//   atomics.
+constexpr int kCells = 2048;
+
+template <bool RESERVE>
 __global__ __launch_bounds__(kBlock) void k_emit(const float4 *__restrict__ rec, const uint32_t *__restrict__ count,
                                                  const uint32_t *__restrict__ partial, uint32_t *__restrict__ offset,
                                                  int n, int TX, const uint32_t *__restrict__ misc,
-                                                 uint32_t *__restrict__ tcnt, uint64_t *__restrict__ bucket) {
+                                                 uint32_t *__restrict__ tcnt, uint32_t *__restrict__ grp_off,
+                                                 uint32_t *__restrict__ inst_off, uint64_t *__restrict__ bucket) {
     if (misc[1] != 0u) return;  // capacity exceeded: nothing downstream runs
     __shared__ uint32_t tmp4[kBlock / kWave];
     __shared__ uint32_t s_incl[kBlock];
     __shared__ uint32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock], s_dbits[kBlock];
-    const int tid = threadIdx.x, gi = blockIdx.x * kBlock + tid;
+    __shared__ uint32_t s_cell[kCells];
+    __shared__ uint32_t s_box[4][kBlock / kWave];
+    const int tid = threadIdx.x, gi = blockIdx.x * kBlock + tid, wv = tid / kWave;
     const uint32_t cnt = gi < n ? count[gi] : 0u;
-    if (COUNT) {
-        const uint32_t excl = block_excl_scan_256(cnt, tmp4);
-        if (gi < n) offset[gi] = partial[blockIdx.x] + excl;
-    }
+    const uint32_t excl = block_excl_scan_256(cnt, tmp4);
+    const uint32_t boff = partial[blockIdx.x];
+    if (RESERVE && gi < n) offset[gi] = boff + excl;
     s_incl[tid] = wave_incl_scan(cnt);
+    uint32_t bx0 = 0xffffu, by0 = 0xffffu, bx1 = 0u, by1 = 0u;
     if (cnt) {
         const float4 r2 = rec[3 * (size_t)gi + 2];
         const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
-        s_x0[tid] = lo & 0xffffu;
-        s_y0[tid] = lo >> 16;
-        s_w[tid] = (hi & 0xffffu) - (lo & 0xffffu);
+        bx0 = lo & 0xffffu;
+        by0 = lo >> 16;
+        bx1 = hi & 0xffffu;
+        by1 = hi >> 16;
+        s_x0[tid] = bx0;
+        s_y0[tid] = by0;
+        s_w[tid] = bx1 - bx0;
         s_dbits[tid] = __float_as_uint(r2.y);
     }
+    // union rectangle of the block's splats
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        bx0 = min(bx0, (uint32_t)__shfl_xor((int)bx0, o, kWave));
+        by0 = min(by0, (uint32_t)__shfl_xor((int)by0, o, kWave));
+        bx1 = max(bx1, (uint32_t)__shfl_xor((int)bx1, o, kWave));
+        by1 = max(by1, (uint32_t)__shfl_xor((int)by1, o, kWave));
+    }
+    if (lane_id() == 0) {
+        s_box[0][wv] = bx0;
+        s_box[1][wv] = by0;
+        s_box[2][wv] = bx1;
+        s_box[3][wv] = by1;
+    }
     __syncthreads();
-    const int wbase = (tid / kWave) * kWave;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) {
+        bx0 = min(bx0, s_box[0][i]);
+        by0 = min(by0, s_box[1][i]);
+        bx1 = max(bx1, s_box[2][i]);
+        by1 = max(by1, s_box[3][i]);
+    }
+    const uint32_t uw = bx1 > bx0 ? bx1 - bx0 : 0u, uh = by1 > by0 ? by1 - by0 : 0u;
+    const bool grouped = uw * uh <= (uint32_t)kCells;
+    if (grouped)
+        for (uint32_t c = tid; c < uw * uh; c += kBlock) s_cell[c] = 0u;
+    __syncthreads();
+    const int wbase = wv * kWave;
     const uint32_t wtotal = s_incl[wbase + kWave - 1];
+    const uint32_t wstart = boff + __shfl(excl, 0, kWave);  // emission position of the wave's first instance
     for (uint32_t j = lane_id(); j < wtotal; j += kWave) {
         int lo = 0, hi = kWave - 1;  // owner: first lane whose inclusive prefix exceeds j
         while (lo < hi) {
@@ -122,12 +171,31 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4 *__restrict__ rec,
         const int o = wbase + lo;
         const uint32_t kk = j - (lo > 0 ? s_incl[o - 1] : 0u);
         const uint32_t w = s_w[o];
-        const uint32_t tile = (s_y0[o] + kk / w) * (uint32_t)TX + (s_x0[o] + kk % w);
-        if (COUNT) {
-            atomicAdd(&tcnt[tile], 1u);
+        const uint32_t tyy = s_y0[o] + kk / w, txx = s_x0[o] + kk % w;
+        const uint32_t tile = tyy * (uint32_t)TX + txx;
+        const uint32_t cell = (tyy - by0) * uw + (txx - bx0);
+        if (RESERVE) {
+            if (grouped)
+                atomicAdd(&s_cell[cell], 1u);
+            else
+                inst_off[wstart + j] = atomicAdd(&tcnt[tile], 1u);
         } else {
-            const uint32_t pos = atomicAdd(&tcnt[tile], 1u);
+            uint32_t pos;
+            if (grouped)
+                pos = tcnt[tile] + grp_off[(size_t)blockIdx.x * kCells + cell] + atomicAdd(&s_cell[cell], 1u);
+            else
+                pos = tcnt[tile] + inst_off[wstart + j];
             bucket[pos] = ((uint64_t)s_dbits[o] << 32) | (uint32_t)(blockIdx.x * kBlock + o);
+        }
+    }
+    if (RESERVE && grouped) {
+        __syncthreads();
+        for (uint32_t c = tid; c < uw * uh; c += kBlock) {
+            const uint32_t k = s_cell[c];
+            if (k) {
+                const uint32_t tile = (by0 + c / uw) * (uint32_t)TX + (bx0 + c % uw);
+                grp_off[(size_t)blockIdx.x * kCells + c] = atomicAdd(&tcnt[tile], k);
+            }
         }
     }
 }
@@ -271,22 +339,28 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-// workspace: bucket keys [cap] u64, alt keys [cap] u64, tile counters [tiles], misc [64]
+// workspace: bucket keys [cap] u64, alt keys [cap] u64 (its first half doubles as the
+// per-instance reservations of the emission, which are dead before the tile sort runs),
+// group reservations [blocks][kCells] u32, tile counters [tiles], misc [64]
 size_t sort_workspace_bytes(int n, int64_t capacity, int tiles) {
-    (void)n;
     const int64_t cap = capacity > 0 ? capacity : 1;
-    return align256(cap * 8) * 2 + align256((size_t)(tiles > 0 ? tiles : 1) * 4) + align256(64 * 4);
+    const size_t nb = (size_t)((n > 0 ? n : 1) + kBlock - 1) / kBlock;
+    return align256(cap * 8) * 2 + align256(nb * kCells * 4) + align256((size_t)(tiles > 0 ? tiles : 1) * 4) +
+           align256(64 * 4);
 }
 
 SortWs carve_workspace(void *ws, int n, int64_t capacity, int tiles) {
-    (void)n;
     const int64_t cap = capacity > 0 ? capacity : 1;
+    const size_t nb = (size_t)((n > 0 ? n : 1) + kBlock - 1) / kBlock;
     SortWs w;
     char *p = (char *)ws;
     w.bucket = (uint64_t *)p;
     p += align256(cap * 8);
     w.alt = (uint64_t *)p;
+    w.inst_off = (uint32_t *)p;
     p += align256(cap * 8);
+    w.grp_off = (uint32_t *)p;
+    p += align256(nb * kCells * 4);
     w.tcnt = (uint32_t *)p;
     p += align256((size_t)(tiles > 0 ? tiles : 1) * 4);
     w.misc = (uint32_t *)p;
@@ -302,11 +376,11 @@ hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *o
                        ws.misc, d_status, ws.tcnt, tiles);
     if (nb > 0)
         hipLaunchKernelGGL(k_emit<true>, dim3(nb), dim3(kBlock), 0, st, rec, count, partial, offset, n, c.TX,
-                           ws.misc, ws.tcnt, ws.bucket);
+                           ws.misc, ws.tcnt, ws.grp_off, ws.inst_off, ws.bucket);
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanThreads), 0, st, ws.tcnt, tiles, ranges, ws.misc);
     if (nb > 0)
         hipLaunchKernelGGL(k_emit<false>, dim3(nb), dim3(kBlock), 0, st, rec, count, partial, offset, n, c.TX,
-                           ws.misc, ws.tcnt, ws.bucket);
+                           ws.misc, ws.tcnt, ws.grp_off, ws.inst_off, ws.bucket);
     hipLaunchKernelGGL(k_tile_sort, dim3(tiles), dim3(kWave), 0, st, ws.bucket, ws.alt, ranges, tiles, keys, vals,
                        ws.misc);
     return hipGetLastError();

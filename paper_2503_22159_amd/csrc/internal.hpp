@@ -131,8 +131,10 @@ struct BatchArgs {
 hipError_t launch_project_batch(const SceneK &s, const BatchArgs &args, hipStream_t st);
 
 struct SortWs {
-    uint64_t *bucket;  // [capacity] per-tile buckets of (depth bits << 32 | gaussian)
-    uint64_t *alt;     // [capacity] scratch of the large-bucket radix sort
+    uint64_t *bucket;    // [capacity] per-tile buckets of (depth bits << 32 | gaussian)
+    uint64_t *alt;       // [capacity] scratch of the large-bucket radix sort
+    uint32_t *inst_off;  // [capacity] per-instance bucket reservations (aliases alt)
+    uint32_t *grp_off;   // [blocks][kCells] per-(block, tile) bucket reservations
     uint32_t *tcnt;    // [tiles] tile counters, then bucket cursors
     uint32_t *misc;    // [64]: [0] instances kept, [1] status
 };

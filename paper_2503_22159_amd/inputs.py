@@ -114,10 +114,11 @@ def _log_uniform(rng, lo, hi, n):
 
 def make_scene(seed, n, sh_degree, *, box=None, clusters=None, cluster_box=None, cluster_std=0.8,
                log_scale=(-3.0, 0.3), dc=(0.5, 0.2), rest_std=0.05, t_scale_range=(0.05, 0.5),
-               vel_std=0.2) -> Scene:
+               vel_std=0.2, morton=True) -> Scene:
     """Draw a scene.  Draw order (fixed): cluster centres, cluster assignment,
     offsets (or uniform means), log-scales, quaternions, opacity logits, SH,
-    temporal means, log temporal scales, velocities."""
+    temporal means, log temporal scales, velocities.  The Gaussians are then stored in
+    3D Morton order of their means (a storage order; any order renders the same set)."""
     rng = np.random.default_rng(seed)
     if clusters:
         lo, hi = cluster_box
@@ -142,7 +143,32 @@ def make_scene(seed, n, sh_degree, *, box=None, clusters=None, cluster_box=None,
     vel = rng.normal(0.0, vel_std, (3, n))
     raw = dict(mean=mean, log_scale=log_s, quat=quat, logit=logit, sh=sh, t_mean=t_mean,
                log_t_scale=log_st, velocity=vel)
+    if morton:
+        order = morton_order(mean)
+        raw = {k: np.ascontiguousarray(v[..., order]) for k, v in raw.items()}
     return scene_from_raw(raw, sh_degree)
+
+
+def _spread10(x):
+    """Spread the low 10 bits of x to every third bit."""
+    x = x.astype(np.uint64) & np.uint64(0x3FF)
+    x = (x | (x << np.uint64(16))) & np.uint64(0x030000FF)
+    x = (x | (x << np.uint64(8))) & np.uint64(0x0300F00F)
+    x = (x | (x << np.uint64(4))) & np.uint64(0x030C30C3)
+    x = (x | (x << np.uint64(2))) & np.uint64(0x09249249)
+    return x
+
+
+def morton_order(mean):
+    """Indices that sort points (3, N) along a 3D Morton (Z-order) curve over their
+    bounding box, 10 bits per axis.  Storing a scene in this order keeps Gaussians that
+    are close in space close in memory: a block of consecutive Gaussians then covers a
+    small part of the screen from any viewpoint."""
+    lo = mean.min(axis=1, keepdims=True)
+    span = np.maximum(mean.max(axis=1, keepdims=True) - lo, 1e-12)
+    q = np.clip(((mean - lo) / span * 1023.0).astype(np.int64), 0, 1023)
+    code = _spread10(q[0]) | (_spread10(q[1]) << np.uint64(1)) | (_spread10(q[2]) << np.uint64(2))
+    return np.argsort(code, kind="stable")
 
 
 def scene_from_raw(raw, sh_degree) -> Scene:
