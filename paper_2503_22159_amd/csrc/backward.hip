@@ -52,6 +52,8 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
     const int px = tx * kTile + (ln & 15);
     const size_t plane = (size_t)c.W * c.H;
     const float sx = (float)px + 0.5f;
+    const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + (float)(kTile - 1);
+    const float wy0 = (float)(ty * kTile) + 0.5f, wy1 = wy0 + (float)(kTile - 1);
     float sy[kPx], Tc[kPx], S0[kPx], S1[kPx], S2[kPx], g0[kPx], g1[kPx], g2[kPx];
     uint32_t nc[kPx];
     uint32_t nmax = 0;
@@ -101,6 +103,16 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
         for (int i = (int)(jb - j0) - 1; i >= 0; --i) {
             const float4 f0 = s0[i], f1 = s1[i], f2 = s2[i], f3 = s3[i];
             const uint32_t jj = j0 - start + (uint32_t)i;  // position in the tile's list
+            if (__builtin_amdgcn_readfirstlane((int)splat_misses(f0, f2, wx0, wx1, wy0, wy1))) {
+                // no pixel of the tile can reach alpha >= 1/255: zero gradient
+                const uint32_t slot = __float_as_uint(f3.w);
+                if (ln == 0 && slot < capacity) {
+                    ig[3 * (size_t)slot + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    ig[3 * (size_t)slot + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    ig[3 * (size_t)slot + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                continue;
+            }
             const float dx = sx - f0.x;
             const ColTerms ct = col_terms(f0, f1, dx);
             const float amax = f2.y;

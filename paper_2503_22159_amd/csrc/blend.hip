@@ -18,6 +18,9 @@ namespace d4 {
 
 namespace {
 
+// A pixel's "done" state (saturated, or outside the image) is the sign bit of its
+// transmittance: a negative T makes every later T' = T (1 - alpha) fall below 1e-4, so the
+// pixel neither blends nor changes; |T| is the transmittance.
 template <int PX, bool STATE>
 __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                  const uint32_t *__restrict__ ranges, CamK c, float bg0, float bg1,
@@ -33,55 +36,71 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     const int ln = lane_id();
     const int px = tx * kTile + (ln & 15);
     const float sx = (float)px + 0.5f;
+    // pixel-centre box of this wavefront (for skipping splats that cannot reach it)
+    const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + (float)(kTile - 1);
+    const float wy0 = (float)(ty * kTile + 4 * sub * PX) + 0.5f, wy1 = wy0 + (float)(4 * PX - 1);
     float sy[PX], T[PX], C0[PX], C1[PX], C2[PX];
-    bool in[PX], done[PX];
     uint32_t last[PX];
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
         const int py = ty * kTile + (ln >> 4) + 4 * (sub * PX + k);
         sy[k] = (float)py + 0.5f;
-        in[k] = px < c.W && py < c.H;
-        done[k] = !in[k];
-        T[k] = 1.0f;
+        T[k] = (px < c.W && py < c.H) ? 1.0f : -1.0f;
         C0[k] = C1[k] = C2[k] = 0.0f;
         last[k] = 0u;
     }
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    // software pipeline: list entries two batches ahead, records one batch ahead
+    float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
+    if (start + ln < end) {
+        const uint32_t g = vals[start + ln];
+        n0 = rec[3 * (size_t)g];
+        n1 = rec[3 * (size_t)g + 1];
+        n2 = rec[3 * (size_t)g + 2];
+    }
+    uint32_t gnext = start + kWave + ln < end ? vals[start + kWave + ln] : 0u;
     for (uint32_t j0 = start; j0 < end; j0 += kWave) {
         bool lane_done = true;
 #pragma unroll
-        for (int k = 0; k < PX; ++k) lane_done = lane_done && done[k];
+        for (int k = 0; k < PX; ++k) lane_done = lane_done && T[k] < 0.0f;
         if (__all(lane_done)) break;
-        const uint32_t j = j0 + ln;
-        if (j < end) {
+        if (j0 + ln < end) {
             float4 f0, f1, f2;
-            fold_splat(rec, vals[j], f0, f1, f2);
+            fold_raw(n0, n1, n2, f0, f1, f2);
             s0[ln] = f0;
             s1[ln] = f1;
             s2[ln] = f2;
         }
         __syncthreads();
+        if (j0 + kWave + ln < end) {
+            n0 = rec[3 * (size_t)gnext];
+            n1 = rec[3 * (size_t)gnext + 1];
+            n2 = rec[3 * (size_t)gnext + 2];
+        }
+        if (j0 + 2 * kWave + ln < end) gnext = vals[j0 + 2 * kWave + ln];
         const uint32_t nb = min((uint32_t)kWave, end - j0);
         for (uint32_t i = 0; i < nb; ++i) {
-            const float4 f0 = s0[i], f1 = s1[i], f2 = s2[i];
+            const float4 f0 = s0[i], f2 = s2[i];
+            if (__builtin_amdgcn_readfirstlane((int)splat_misses(f0, f2, wx0, wx1, wy0, wy1))) continue;
+            const float4 f1 = s1[i];
             const ColTerms ct = col_terms(f0, f1, sx - f0.x);
             bool all_done = true;
 #pragma unroll
             for (int k = 0; k < PX; ++k) {
                 const float q = pix_exponent(ct, f1, sy[k] - f0.y);
                 const float alpha = fminf(kAlphaMax, exp2_fast(q));
-                const bool ok = !done[k] && !(q > f1.y) && alpha >= kAlphaMin;
-                const float Tn = T[k] * (1.0f - alpha);
+                const bool ok = !(q > f1.y) && alpha >= kAlphaMin;
+                const float Tk = T[k];
+                const float Tn = Tk * (1.0f - alpha);
                 const bool stop = ok && Tn < kTMin;
                 const bool blend = ok && !stop;
-                const float wgt = blend ? alpha * T[k] : 0.0f;
+                const float wgt = blend ? alpha * Tk : 0.0f;
                 C0[k] = __builtin_fmaf(f1.z, wgt, C0[k]);
                 C1[k] = __builtin_fmaf(f1.w, wgt, C1[k]);
                 C2[k] = __builtin_fmaf(f2.x, wgt, C2[k]);
-                T[k] = blend ? Tn : T[k];
+                T[k] = blend ? Tn : (stop ? -fabsf(Tk) : Tk);
                 if (STATE) last[k] = blend ? (j0 - start + i + 1) : last[k];
-                done[k] = done[k] || stop;
-                all_done = all_done && done[k];
+                all_done = all_done && T[k] < 0.0f;
             }
             if (__all(all_done)) break;
         }
@@ -90,14 +109,15 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     const size_t plane = (size_t)c.W * c.H;
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
-        if (!in[k]) continue;
         const int py = ty * kTile + (ln >> 4) + 4 * (sub * PX + k);
+        if (px >= c.W || py >= c.H) continue;
         const size_t pi = (size_t)py * c.W + px;
-        img[pi] = C0[k] + T[k] * bg0;
-        img[plane + pi] = C1[k] + T[k] * bg1;
-        img[2 * plane + pi] = C2[k] + T[k] * bg2;
+        const float Tk = fabsf(T[k]);
+        img[pi] = C0[k] + Tk * bg0;
+        img[plane + pi] = C1[k] + Tk * bg1;
+        img[2 * plane + pi] = C2[k] + Tk * bg2;
         if (STATE) {
-            final_T[pi] = T[k];
+            final_T[pi] = Tk;
             ncontrib[pi] = last[k];
         }
     }

@@ -78,14 +78,42 @@ __device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_lo
 // Per lane the terms that depend only on dx are formed once and shared by the lane's
 // pixels, which lie in one column:  A0 = qa dx dx + la,  B0 = qb dx,
 //   q = (qc dy + B0) dy + A0.
-__device__ __forceinline__ void fold_splat(const float4 *__restrict__ rec, uint32_t gi, float4 &f0, float4 &f1,
-                                           float4 &f2) {
-    const float4 p = rec[3 * (size_t)gi + 0];
-    const float4 q = rec[3 * (size_t)gi + 1];
-    const float4 s = rec[3 * (size_t)gi + 2];
+//
+// f2.z, f2.w are the half-extents (x, y) of the ellipse where alpha can reach 1/255:
+// amax exp(power) >= 1/255 needs power >= -L, L = ln(255 amax), and -power =
+// 1/2 d^T Q d (Q the conic), so |dx| <= sqrt(2 L Sigma'_xx), |dy| <= sqrt(2 L Sigma'_yy)
+// with Sigma' = Q^-1.  Inflated by 1% + 0.05 px, far beyond FP32 rounding, a splat whose
+// box misses every pixel centre of a wavefront is skipped by that whole wavefront without
+// changing any decision: every pixel would have skipped it.  -1 marks a splat that can
+// never reach 1/255 (amax < 1/255).
+__device__ __forceinline__ void fold_raw(const float4 &p, const float4 &q, const float4 &s, float4 &f0, float4 &f1,
+                                         float4 &f2) {
     f0 = make_float4(p.x, p.y, (-0.5f * kLog2e) * p.z, (-kLog2e) * p.w);
     f1 = make_float4((-0.5f * kLog2e) * q.x, log2_fast(q.y), q.z, q.w);
-    f2 = make_float4(s.x, q.y, 0.0f, 0.0f);
+    const float L = (7.99435344f + f1.y) * 0.69314718f;  // ln(255 amax) = (log2 255 + log2 amax) ln 2
+    const float det = p.z * q.x - p.w * p.w;
+    float ex, ey;
+    if (L < -1e-4f) {  // amax clearly below 1/255: no pixel can keep it
+        ex = ey = -1.0f;
+    } else if (det > 0.0f) {
+        const float k2 = 2.0f * fmaxf(L, 0.0f) / det;
+        ex = sqrtf(k2 * q.x) * 1.01f + 0.05f;
+        ey = sqrtf(k2 * p.z) * 1.01f + 0.05f;
+    } else {  // conic degenerate in FP32: never skip
+        ex = ey = 3.0e38f;
+    }
+    f2 = make_float4(s.x, q.y, ex, ey);
+}
+
+__device__ __forceinline__ void fold_splat(const float4 *__restrict__ rec, uint32_t gi, float4 &f0, float4 &f1,
+                                           float4 &f2) {
+    fold_raw(rec[3 * (size_t)gi + 0], rec[3 * (size_t)gi + 1], rec[3 * (size_t)gi + 2], f0, f1, f2);
+}
+
+// True if the splat's alpha >= 1/255 box misses the pixel-centre box [x0,x1] x [y0,y1].
+__device__ __forceinline__ bool splat_misses(const float4 &f0, const float4 &f2, float x0, float x1, float y0,
+                                             float y1) {
+    return f2.z < 0.0f || f0.x + f2.z < x0 || f0.x - f2.z > x1 || f0.y + f2.w < y0 || f0.y - f2.w > y1;
 }
 
 struct ColTerms {
