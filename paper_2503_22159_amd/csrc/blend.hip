@@ -18,15 +18,22 @@ namespace d4 {
 
 namespace {
 
-// A pixel's "done" state (saturated, or outside the image) is the sign bit of its
-// transmittance: a negative T makes every later T' = T (1 - alpha) fall below 1e-4, so the
-// pixel neither blends nor changes; |T| is the transmittance.
+// Per pixel row k, "done" (saturated, or outside the image) is a wave-uniform lane mask kept
+// in scalar registers; the per-pixel skip / stop / blend decisions are formed as lane masks
+// (ballots of the compares) and applied with inverse ballots.  A done pixel neither blends
+// nor changes: T keeps the transmittance it had before the splat that stopped it.
+//
+// Staging culls: each lane tests its own splat's alpha >= 1/255 box against the wavefront's
+// pixel-centre box and only the splats that can reach one of its pixels are parked, compacted
+// in list order (ballot + lane-rank), so the per-splat loop carries no test.
 template <int PX, bool STATE>
 __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                  const uint32_t *__restrict__ ranges, CamK c, float bg0, float bg1,
                                                  float bg2, float *__restrict__ img, float *__restrict__ final_T,
                                                  uint32_t *__restrict__ ncontrib, int nlogical, int per_xcd) {
     constexpr int WPT = 4 / PX;  // waves per tile
+    // s2[i] = {b, bits(list position + 1), -, -}: strided like s0 and s1 so that one address
+    // register serves all three reads
     __shared__ float4 s0[kWave], s1[kWave], s2[kWave];
     const int b = blockIdx.x;
     const int L = (b & 7) * per_xcd + (b >> 3);
@@ -40,12 +47,14 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + (float)(kTile - 1);
     const float wy0 = (float)(ty * kTile + 4 * sub * PX) + 0.5f, wy1 = wy0 + (float)(4 * PX - 1);
     float sy[PX], T[PX], C0[PX], C1[PX], C2[PX];
+    uint64_t done[PX];
     uint32_t last[PX];
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
         const int py = ty * kTile + (ln >> 4) + 4 * (sub * PX + k);
         sy[k] = (float)py + 0.5f;
-        T[k] = (px < c.W && py < c.H) ? 1.0f : -1.0f;
+        T[k] = 1.0f;
+        done[k] = __ballot(!(px < c.W && py < c.H));
         C0[k] = C1[k] = C2[k] = 0.0f;
         last[k] = 0u;
     }
@@ -60,16 +69,24 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     }
     uint32_t gnext = start + kWave + ln < end ? vals[start + kWave + ln] : 0u;
     for (uint32_t j0 = start; j0 < end; j0 += kWave) {
-        bool lane_done = true;
+        uint64_t all_done = ~0ull;
 #pragma unroll
-        for (int k = 0; k < PX; ++k) lane_done = lane_done && T[k] < 0.0f;
-        if (__all(lane_done)) break;
+        for (int k = 0; k < PX; ++k) all_done &= done[k];
+        if (all_done == ~0ull) break;
+        bool keep = false;
+        float4 f0, f1, f2;
         if (j0 + ln < end) {
-            float4 f0, f1, f2;
             fold_raw(n0, n1, n2, f0, f1, f2);
-            s0[ln] = f0;
-            s1[ln] = f1;
-            s2[ln] = f2;
+            keep = !splat_misses(f0, f2, wx0, wx1, wy0, wy1);
+        }
+        const uint64_t km = __ballot(keep);
+        if (keep) {
+            const int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+            s0[pos] = f0;
+            s1[pos] = f1;
+            s2[pos].x = f2.x;
+            if (STATE) s2[pos].y = __uint_as_float(j0 - start + ln + 1);
         }
         __syncthreads();
         if (j0 + kWave + ln < end) {
@@ -78,31 +95,31 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
             n2 = rec[3 * (size_t)gnext + 2];
         }
         if (j0 + 2 * kWave + ln < end) gnext = vals[j0 + 2 * kWave + ln];
-        const uint32_t nb = min((uint32_t)kWave, end - j0);
-        for (uint32_t i = 0; i < nb; ++i) {
-            const float4 f0 = s0[i], f2 = s2[i];
-            if (__builtin_amdgcn_readfirstlane((int)splat_misses(f0, f2, wx0, wx1, wy0, wy1))) continue;
-            const float4 f1 = s1[i];
-            const ColTerms ct = col_terms(f0, f1, sx - f0.x);
-            bool all_done = true;
+        const int nb = __popcll(km);
+        for (int i = 0; i < nb; ++i) {
+            const float4 g0 = s0[i], g1 = s1[i];
+            const float cb = s2[i].x;
+            const ColTerms ct = col_terms(g0, g1, sx - g0.x);
+            uint64_t all = ~0ull;
 #pragma unroll
             for (int k = 0; k < PX; ++k) {
-                const float q = pix_exponent(ct, f1, sy[k] - f0.y);
+                const float q = pix_exponent(ct, g1, sy[k] - g0.y);
                 const float alpha = fminf(kAlphaMax, exp2_fast(q));
-                const bool ok = !(q > f1.y) && alpha >= kAlphaMin;
+                const uint64_t ok = __ballot(!(q > g1.y)) & __ballot(alpha >= kAlphaMin) & ~done[k];
                 const float Tk = T[k];
-                const float Tn = Tk * (1.0f - alpha);
-                const bool stop = ok && Tn < kTMin;
-                const bool blend = ok && !stop;
+                const float Tn = __builtin_fmaf(-alpha, Tk, Tk);  // T (1 - alpha)
+                const uint64_t stop = ok & __ballot(Tn < kTMin);
+                const bool blend = __builtin_amdgcn_inverse_ballot_w64(ok & ~stop);
+                done[k] |= stop;
                 const float wgt = blend ? alpha * Tk : 0.0f;
-                C0[k] = __builtin_fmaf(f1.z, wgt, C0[k]);
-                C1[k] = __builtin_fmaf(f1.w, wgt, C1[k]);
-                C2[k] = __builtin_fmaf(f2.x, wgt, C2[k]);
-                T[k] = blend ? Tn : (stop ? -fabsf(Tk) : Tk);
-                if (STATE) last[k] = blend ? (j0 - start + i + 1) : last[k];
-                all_done = all_done && T[k] < 0.0f;
+                C0[k] = __builtin_fmaf(g1.z, wgt, C0[k]);
+                C1[k] = __builtin_fmaf(g1.w, wgt, C1[k]);
+                C2[k] = __builtin_fmaf(cb, wgt, C2[k]);
+                T[k] = blend ? Tn : Tk;
+                if (STATE) last[k] = blend ? __float_as_uint(s2[i].y) : last[k];
+                all &= done[k];
             }
-            if (__all(all_done)) break;
+            if (all == ~0ull) break;
         }
         __syncthreads();
     }
@@ -112,12 +129,11 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
         const int py = ty * kTile + (ln >> 4) + 4 * (sub * PX + k);
         if (px >= c.W || py >= c.H) continue;
         const size_t pi = (size_t)py * c.W + px;
-        const float Tk = fabsf(T[k]);
-        img[pi] = C0[k] + Tk * bg0;
-        img[plane + pi] = C1[k] + Tk * bg1;
-        img[2 * plane + pi] = C2[k] + Tk * bg2;
+        img[pi] = C0[k] + T[k] * bg0;
+        img[plane + pi] = C1[k] + T[k] * bg1;
+        img[2 * plane + pi] = C2[k] + T[k] * bg2;
         if (STATE) {
-            final_T[pi] = Tk;
+            final_T[pi] = T[k];
             ncontrib[pi] = last[k];
         }
     }
