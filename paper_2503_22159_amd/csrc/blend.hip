@@ -1,17 +1,20 @@
 // Per-tile front-to-back alpha blending (Eq. 4 with alpha_i = o_i w_i G'_i).
 //
-// A 16x16 tile is rendered by 4 / PX wavefronts (one workgroup each), PX pixels per lane:
-// lane l owns column l % 16 and rows l / 16 + 4 k of its wave's band.  Each wavefront walks
-// the tile's depth-sorted list in batches of 64: every lane gathers one splat record,
-// folds it (exponent constants, log2 of the peak opacity) and parks it in LDS; then the
-// wave steps through the batch reading each splat as an LDS broadcast.  No block-wide
-// barriers (a workgroup is one wave).  The terms of the exponent that depend only on the
-// column are formed once per lane and shared by its pixels.  A wave stops as soon as all
-// of its pixels are saturated (wave-wide vote).
+// A 16x16 tile is rendered by 4 / PX wavefronts (one workgroup each).  Each wavefront owns
+// an RW x (64 / RW) PX pixel region of the tile: lane l has column l % RW and rows
+// l / RW + (64 / RW) k, k < PX.  Each wavefront walks the tile's depth-sorted list in
+// batches of 64: every lane gathers one splat record, folds it (exponent constants, log2
+// of the peak opacity) and parks it in LDS; then the wave steps through the batch reading
+// each splat as an LDS broadcast.  No block-wide barriers (a workgroup is one wave).  The
+// terms of the exponent that depend only on the column are formed once per lane and
+// shared by its pixels.  A wave stops as soon as all of its pixels are saturated.
 //
 // Launch order is XCD-aware: the hardware deals consecutive workgroups round-robin to the
 // 8 XCDs, so block b takes logical block (b % 8) * per_xcd + b / 8 -- each XCD renders a
 // contiguous band of tiles, and neighbouring tiles, which share splats, share its L2.
+#include <stdio.h>
+#include <stdlib.h>
+
 #include "internal.hpp"
 
 namespace d4 {
@@ -26,12 +29,16 @@ namespace {
 // Staging culls: each lane tests its own splat's alpha >= 1/255 box against the wavefront's
 // pixel-centre box and only the splats that can reach one of its pixels are parked, compacted
 // in list order (ballot + lane-rank), so the per-splat loop carries no test.
-template <int PX, bool STATE>
+template <int PX, int RW, bool STATE>
 __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                  const uint32_t *__restrict__ ranges, CamK c, float bg0, float bg1,
                                                  float bg2, float *__restrict__ img, float *__restrict__ final_T,
                                                  uint32_t *__restrict__ ncontrib, int nlogical, int per_xcd) {
-    constexpr int WPT = 4 / PX;  // waves per tile
+    constexpr int LR = kWave / RW;      // lane rows
+    constexpr int RH = LR * PX;         // rows of the wavefront's pixel region (RW x RH)
+    constexpr int NXR = kTile / RW;     // regions across a tile
+    constexpr int WPT = 4 / PX;         // waves per tile
+    static_assert(RH <= kTile && (RW == 8 || RW == 16), "wavefront region must tile a 16x16 tile");
     // s2[i] = {b, bits(list position + 1), -, -}: strided like s0 and s1 so that one address
     // register serves all three reads
     __shared__ float4 s0[kWave], s1[kWave], s2[kWave];
@@ -40,18 +47,19 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     if (L >= nlogical) return;
     const int tile = L / WPT, sub = L % WPT;
     const int tx = tile % c.TX, ty = tile / c.TX;
+    const int rx0 = tx * kTile + (sub % NXR) * RW, ry0 = ty * kTile + (sub / NXR) * RH;
     const int ln = lane_id();
-    const int px = tx * kTile + (ln & 15);
+    const int px = rx0 + ln % RW;
     const float sx = (float)px + 0.5f;
     // pixel-centre box of this wavefront (for skipping splats that cannot reach it)
-    const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + (float)(kTile - 1);
-    const float wy0 = (float)(ty * kTile + 4 * sub * PX) + 0.5f, wy1 = wy0 + (float)(4 * PX - 1);
+    const float wx0 = (float)rx0 + 0.5f, wx1 = wx0 + (float)(RW - 1);
+    const float wy0 = (float)ry0 + 0.5f, wy1 = wy0 + (float)(RH - 1);
     float sy[PX], T[PX], C0[PX], C1[PX], C2[PX];
     uint64_t done[PX];
     uint32_t last[PX];
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
-        const int py = ty * kTile + (ln >> 4) + 4 * (sub * PX + k);
+        const int py = ry0 + ln / RW + LR * k;
         sy[k] = (float)py + 0.5f;
         T[k] = 1.0f;
         done[k] = __ballot(!(px < c.W && py < c.H));
@@ -126,7 +134,7 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     const size_t plane = (size_t)c.W * c.H;
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
-        const int py = ty * kTile + (ln >> 4) + 4 * (sub * PX + k);
+        const int py = ry0 + ln / RW + LR * k;
         if (px >= c.W || py >= c.H) continue;
         const size_t pi = (size_t)py * c.W + px;
         img[pi] = C0[k] + T[k] * bg0;
@@ -139,28 +147,30 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     }
 }
 
-template <int PX>
+template <int PX, int RW>
 void launch_px(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c, const float bg[3],
                float *img, float *final_T, uint32_t *n_contrib, hipStream_t st) {
     const int nlogical = c.TX * c.TY * (4 / PX);
     const int per_xcd = (nlogical + 7) / 8;
     if (final_T)
-        hipLaunchKernelGGL((k_blend<PX, true>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c, bg[0],
-                           bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd);
+        hipLaunchKernelGGL((k_blend<PX, RW, true>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c,
+                           bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd);
     else
-        hipLaunchKernelGGL((k_blend<PX, false>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c, bg[0],
-                           bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd);
+        hipLaunchKernelGGL((k_blend<PX, RW, false>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c,
+                           bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd);
 }
 
-// Pixels per lane of the forward blend: 2 (measured best at 1352x1014); D4DGS_BLEND_PX
-// selects 4 or 1.
-int blend_px() {
-    static const int px = [] {
-        const char *e = getenv("D4DGS_BLEND_PX");
-        const int v = e ? atoi(e) : 2;
-        return (v == 1 || v == 2 || v == 4) ? v : 2;
+// Wavefront pixel region: PX pixels per lane in one column, RW columns wide.  Default 1 x 8
+// (an 8x8 square per wavefront); D4DGS_BLEND=<px>x<rw> selects 1x16, 2x8, 2x16 or 4x16.
+int blend_variant() {
+    static const int v = [] {
+        const char *e = getenv("D4DGS_BLEND");
+        int px = 1, rw = 8;
+        if (e && sscanf(e, "%dx%d", &px, &rw) != 2) px = 1, rw = 8;
+        const int code = px * 100 + rw;
+        return (code == 108 || code == 116 || code == 208 || code == 216 || code == 416) ? code : 108;
     }();
-    return px;
+    return v;
 }
 
 }  // namespace
@@ -168,10 +178,12 @@ int blend_px() {
 hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c,
                         const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st) {
     if (c.TX * c.TY == 0) return hipSuccess;
-    switch (blend_px()) {
-        case 1: launch_px<1>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
-        case 2: launch_px<2>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
-        default: launch_px<4>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
+    switch (blend_variant()) {
+        case 116: launch_px<1, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
+        case 208: launch_px<2, 8>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
+        case 216: launch_px<2, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
+        case 416: launch_px<4, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
+        default: launch_px<1, 8>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
     }
     return hipGetLastError();
 }
