@@ -13,14 +13,16 @@
 //                    owner found by binary search over the wave prefix), so splats with
 //                    large rectangles do not stall a wave.
 //   k_tile_scan      one block: exclusive scan over tiles -> ranges, bucket cursors.
-//   k_tile_sort      one wavefront per tile sorts its bucket by the 64-bit key -- depth,
-//                    ties by Gaussian index, a unique order, so the result does not depend
-//                    on the order the atomics handed out positions.  Buckets of up to 64
-//                    keys: register bitonic network over the wave (cross-lane shuffles);
-//                    up to kLdsSort keys: bitonic network in LDS; larger: least-
-//                    significant-digit radix sort over the 64 key bits, 8-bit digits,
-//                    wave64 ballot ranking, ping-ponging in global scratch.
-//                    Writes keys = (tile << 32) | float-bits(depth) and values = gaussian.
+//   k_tile_sort      one workgroup of 256 per tile sorts its bucket by the 64-bit key --
+//                    depth, ties by Gaussian index: a unique order, so the result does not
+//                    depend on the order the atomics handed out positions.  Buckets of up to
+//                    kRankMax keys are sorted by ranking: the keys are unique, so a key's
+//                    sorted position is the number of smaller keys, counted by each thread
+//                    for its own keys against the bucket broadcast from LDS.  Up to kLdsSort
+//                    keys: bitonic network in LDS; larger: stable least-significant-digit
+//                    radix sort over the 64 key bits, 8-bit digits, ping-ponging in global
+//                    scratch.  Writes keys = (tile << 32) | float-bits(depth) and
+//                    values = gaussian.
 //
 // The instance total lives on the device; no host synchronisation is needed.  If it
 // exceeds the capacity, a status word is set and every later stage does nothing.
@@ -31,7 +33,10 @@ namespace d4 {
 namespace {
 
 constexpr int kScanThreads = 1024;
-constexpr int kLdsSort = 2048;  // largest bucket sorted in LDS
+constexpr int kSortThreads = 256;
+constexpr int kRankMax = 2 * kSortThreads;  // largest bucket sorted by ranking (two keys per thread)
+constexpr int kLdsSort = 2048;              // largest bucket sorted by a bitonic network in LDS
+static_assert(kSortThreads == kBlock && kSortThreads == kRadix, "one digit counter per thread");
 
 __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *tmp4) {
     const int w = threadIdx.x / kWave;
@@ -232,27 +237,28 @@ __device__ __forceinline__ void write_out(uint64_t k, uint32_t pos, uint32_t til
     vals[pos] = (uint32_t)k;
 }
 
-// Stable LSD radix sort of src[0, s) by all 64 key bits, one wavefront, 8-bit digits,
-// ping-ponging between src and alt; returns the buffer holding the result.
-__device__ uint64_t *wave_radix_sort(uint64_t *src, uint64_t *alt, uint32_t s, uint32_t *cnt /* LDS [256] */) {
-    const int ln = lane_id();
+// Stable LSD radix sort of src[0, s) by all 64 key bits, one workgroup of kSortThreads,
+// 8-bit digits, ping-ponging between src and alt; returns the buffer holding the result.
+// Elements are ranked in chunks of kSortThreads: within a wavefront by ballot matching on
+// the digit bits, across the wavefronts of the chunk by per-wave digit counts in LDS.
+__device__ uint64_t *block_radix_sort(uint64_t *src, uint64_t *alt, uint32_t s, uint32_t *cnt /* [kRadix] */,
+                                      uint32_t *wc /* [kSortThreads / kWave][kRadix] */, uint32_t *tmp4) {
+    constexpr int NW = kSortThreads / kWave;
+    const int tid = threadIdx.x, w = tid / kWave;
     const uint64_t lt = lanemask_lt();
     for (int shift = 0; shift < 64; shift += 8) {
-        for (int d = ln; d < kRadix; d += kWave) cnt[d] = 0u;
+        cnt[tid] = 0u;
         __syncthreads();
-        for (uint32_t i = ln; i < s; i += kWave) atomicAdd(&cnt[(uint32_t)(src[i] >> shift) & 0xffu], 1u);
+        for (uint32_t i = tid; i < s; i += kSortThreads) atomicAdd(&cnt[(uint32_t)(src[i] >> shift) & 0xffu], 1u);
         __syncthreads();
-        if (ln == 0) {
-            uint32_t run = 0;
-            for (int d = 0; d < kRadix; ++d) {
-                const uint32_t c = cnt[d];
-                cnt[d] = run;
-                run += c;
-            }
-        }
-        __syncthreads();
-        for (uint32_t r0 = 0; r0 < s; r0 += kWave) {
-            const uint32_t i = r0 + ln;
+        const uint32_t c = cnt[tid];
+        const uint32_t e = block_excl_scan_256(c, tmp4);
+        cnt[tid] = e;
+        for (uint32_t r0 = 0; r0 < s; r0 += kSortThreads) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) wc[q * kRadix + tid] = 0u;
+            __syncthreads();
+            const uint32_t i = r0 + tid;
             const bool valid = i < s;
             const uint64_t k = valid ? src[i] : 0ull;
             const uint32_t d = (uint32_t)(k >> shift) & 0xffu;
@@ -264,12 +270,18 @@ __device__ uint64_t *wave_radix_sort(uint64_t *src, uint64_t *alt, uint32_t s, u
                 peers &= bit ? bb : ~bb;
             }
             const uint32_t rank = __popcll(peers & lt);
-            const uint32_t base = cnt[d];
-            if (valid) alt[base + rank] = k;
+            if (valid && rank == 0) wc[w * kRadix + d] = __popcll(peers);
             __syncthreads();
-            if (valid && rank == 0) cnt[d] = base + __popcll(peers);
+            uint32_t before = 0, total = 0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) before += q < w ? wc[q * kRadix + d] : 0u;
+            if (valid) alt[cnt[d] + before + rank] = k;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) total += wc[q * kRadix + tid];
             __syncthreads();
+            cnt[tid] += total;
         }
+        __syncthreads();
         uint64_t *t = src;
         src = alt;
         alt = t;
@@ -277,44 +289,58 @@ __device__ uint64_t *wave_radix_sort(uint64_t *src, uint64_t *alt, uint32_t s, u
     return src;
 }
 
-__global__ __launch_bounds__(kWave) void k_tile_sort(uint64_t *__restrict__ bucket, uint64_t *__restrict__ alt,
-                                                     const uint32_t *__restrict__ ranges, int tiles,
-                                                     uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                     const uint32_t *__restrict__ misc) {
+__global__ __launch_bounds__(kSortThreads) void k_tile_sort(uint64_t *__restrict__ bucket,
+                                                            uint64_t *__restrict__ alt,
+                                                            const uint32_t *__restrict__ ranges, int tiles,
+                                                            uint64_t *__restrict__ keys,
+                                                            uint32_t *__restrict__ vals,
+                                                            const uint32_t *__restrict__ misc) {
     if (misc[1] != 0u) return;
-    __shared__ uint64_t sk[kLdsSort];
+    __shared__ __align__(16) uint64_t sk[kLdsSort];
     __shared__ uint32_t cnt[kRadix];
+    __shared__ uint32_t tmp4[kSortThreads / kWave];
     const int tile = blockIdx.x;
     if (tile >= tiles) return;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     const uint32_t s = end - start;
-    const int ln = lane_id();
+    const uint32_t tid = threadIdx.x;
     if (s == 0) return;
-    if (s <= (uint32_t)kWave) {
-        // register bitonic sort, one key per lane (padding sorts last)
-        uint64_t k = (uint32_t)ln < s ? bucket[start + ln] : ~0ull;
-#pragma unroll
-        for (int size = 2; size <= kWave; size <<= 1) {
-#pragma unroll
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                const uint64_t o = __shfl_xor(k, stride, kWave);
-                const bool up = (ln & size) == 0;
-                const bool lower = (ln & stride) == 0;
-                const uint64_t mn = k < o ? k : o, mx = k < o ? o : k;
-                k = (lower == up) ? mn : mx;
+    if (s <= (uint32_t)kRankMax) {
+        const uint32_t i1 = tid + kSortThreads;
+        const uint64_t k0 = tid < s ? bucket[start + tid] : ~0ull;
+        const uint64_t k1 = i1 < s ? bucket[start + i1] : ~0ull;
+        // padded to a multiple of 4 with the largest key (never below a real key)
+        const uint32_t s4 = (s + 3u) & ~3u;
+        if (tid < s4) sk[tid] = k0;
+        if (i1 < s4) sk[i1] = k1;
+        __syncthreads();
+        if ((tid & ~(uint32_t)(kWave - 1)) >= s) return;  // a wavefront without keys
+        const ulonglong2 *sk2 = reinterpret_cast<const ulonglong2 *>(sk);
+        uint32_t r0 = 0, r1 = 0;
+        if (s <= (uint32_t)kSortThreads) {
+            for (uint32_t j = 0; j < s4 / 2; j += 2) {
+                const ulonglong2 a = sk2[j], b = sk2[j + 1];
+                r0 += (a.x < k0) + (a.y < k0) + (b.x < k0) + (b.y < k0);
+            }
+        } else {
+            for (uint32_t j = 0; j < s4 / 2; j += 2) {
+                const ulonglong2 a = sk2[j], b = sk2[j + 1];
+                r0 += (a.x < k0) + (a.y < k0) + (b.x < k0) + (b.y < k0);
+                r1 += (a.x < k1) + (a.y < k1) + (b.x < k1) + (b.y < k1);
             }
         }
-        if ((uint32_t)ln < s) write_out(k, start + ln, (uint32_t)tile, keys, vals);
+        if (tid < s) write_out(k0, start + r0, (uint32_t)tile, keys, vals);
+        if (i1 < s) write_out(k1, start + r1, (uint32_t)tile, keys, vals);
         return;
     }
     if (s <= (uint32_t)kLdsSort) {
-        uint32_t P = 128;
+        uint32_t P = 2 * kRankMax;
         while (P < s) P <<= 1;
-        for (uint32_t i = ln; i < P; i += kWave) sk[i] = i < s ? bucket[start + i] : ~0ull;
+        for (uint32_t i = tid; i < P; i += kSortThreads) sk[i] = i < s ? bucket[start + i] : ~0ull;
         __syncthreads();
         for (uint32_t size = 2; size <= P; size <<= 1) {
             for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t p = ln; p < P / 2; p += kWave) {
+                for (uint32_t p = tid; p < P / 2; p += kSortThreads) {
                     const uint32_t i = 2 * p - (p & (stride - 1));  // lower index of the pair
                     const uint32_t j = i + stride;
                     const bool up = (i & size) == 0;
@@ -327,12 +353,13 @@ __global__ __launch_bounds__(kWave) void k_tile_sort(uint64_t *__restrict__ buck
                 __syncthreads();
             }
         }
-        for (uint32_t i = ln; i < s; i += kWave) write_out(sk[i], start + i, (uint32_t)tile, keys, vals);
+        for (uint32_t i = tid; i < s; i += kSortThreads) write_out(sk[i], start + i, (uint32_t)tile, keys, vals);
         return;
     }
-    // large bucket: radix sort in global scratch (same index range of `alt`)
-    uint64_t *res = wave_radix_sort(bucket + start, alt + start, s, cnt);
-    for (uint32_t i = ln; i < s; i += kWave) write_out(res[i], start + i, (uint32_t)tile, keys, vals);
+    // large bucket: radix sort in global scratch (same index range of `alt`); the digit
+    // counts per wavefront reuse the LDS of the bitonic path
+    uint64_t *res = block_radix_sort(bucket + start, alt + start, s, cnt, reinterpret_cast<uint32_t *>(sk), tmp4);
+    for (uint32_t i = tid; i < s; i += kSortThreads) write_out(res[i], start + i, (uint32_t)tile, keys, vals);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -381,7 +408,7 @@ hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *o
     if (nb > 0)
         hipLaunchKernelGGL(k_emit<false>, dim3(nb), dim3(kBlock), 0, st, rec, count, partial, offset, n, c.TX,
                            ws.misc, ws.tcnt, ws.grp_off, ws.inst_off, ws.bucket);
-    hipLaunchKernelGGL(k_tile_sort, dim3(tiles), dim3(kWave), 0, st, ws.bucket, ws.alt, ranges, tiles, keys, vals,
+    hipLaunchKernelGGL(k_tile_sort, dim3(tiles), dim3(kSortThreads), 0, st, ws.bucket, ws.alt, ranges, tiles, keys, vals,
                        ws.misc);
     return hipGetLastError();
 }

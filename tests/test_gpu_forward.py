@@ -83,6 +83,20 @@ def test_c2_full_size_frame(R):
     print("c2 full", stats)
 
 
+@pytest.mark.parametrize("n", [150, 300, 1200, 3000])
+def test_dense_tiles_every_sort_path(R, n):
+    """Large splats over a 48x48 view (9 tiles): every Gaussian lands in every tile, so the
+    buckets hold ~1.2 n keys and take each per-tile sort (ranking up to 512 keys, bitonic
+    network up to 2048, radix sort beyond).  A fifth of the Gaussians are exact copies of
+    others, so equal depths must come out ordered by Gaussian index."""
+    base = inputs.make_scene(50 + n, n, 0, box=(-0.3, 0.3), log_scale=(0.5, 0.1),
+                             t_scale_range=(0.5, 1.0), vel_std=0.0)
+    rng = np.random.default_rng(n)
+    sc = base.subset(np.concatenate([np.arange(n), rng.choice(n, n // 5, replace=False)]))
+    cam = inputs.look_at((0.0, 0.0, -6.0), width=48, height=48)
+    check_frame(R, sc, cam, np.float32(0.5), bg=(0.1, 0.2, 0.3))
+
+
 def test_empty_and_all_culled(R):
     sc, cam, t = inputs.config1()
     empty = sc.subset(np.arange(0))
