@@ -3,16 +3,23 @@
 // k_blend_bwd   one wavefront per 16x16 tile, four pixels per lane, walking the tile's
 //               list from the wave's last contributor back to the front.  Each pixel's
 //               transmittance is replayed backwards from its final value,
-//               T_i = T_{i+1} / (1 - alpha_i), and the suffix colour
-//               S_i = sum_{j>i} c_j alpha_j T_j + T_final bg is carried along, so
-//                 dC/dc_i     = alpha_i T_i
-//                 dC/dalpha_i = c_i T_i - S_i / (1 - alpha_i).
+//               T_i = T_{i+1} / (1 - alpha_i), and, with g = dL/dC the pixel's upstream
+//               gradient and S_i = sum_{j>i} c_j alpha_j T_j + T_final bg the colour
+//               behind splat i, the scalar g.S_i is carried along, so
+//                 dL/dc_i     = g alpha_i T_i
+//                 dL/dalpha_i = (g.c_i) T_i - (g.S_i) / (1 - alpha_i).
 //               No per-splat forward state is stored.  alpha_i is recomputed by the same
-//               instructions as the forward, so skip decisions match exactly.  The nine
-//               per-splat gradients (m, conic, amax, rgb) are summed over the wave and
-//               written to the instance's own slot: slot = offset[g] + position of the
-//               tile inside g's rectangle, i.e. the instance's pre-sort emission index.
-//               Every slot is written exactly once; no atomics.
+//               instructions as the forward, so skip decisions match exactly.
+//               Splats whose alpha >= 1/255 box misses the tile are dropped while a batch
+//               is staged (their gradient is zero); the rest are compacted.  Per splat a
+//               lane sums over its pixels dp = dL/dpower and its moments about the splat
+//               mean (dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2; d = pixel - m) and the
+//               three colour gradients; the wave reduces the nine sums with cross-lane
+//               moves (no LDS), and after the batch one lane per splat turns the moments
+//               into the gradients of the 2D mean, the conic and amax and writes the
+//               instance's own slot: slot = offset[g] + position of the tile inside g's
+//               rectangle, i.e. the instance's pre-sort emission index.  Every slot is
+//               written exactly once; no atomics.
 // k_project_bwd one thread per Gaussian: sums its contiguous slots in a fixed order
 //               (deterministic), then applies the chain rule through the time stage
 //               (alpha_max = o w, w = exp(-tau^2 / 2 s_t^2), m = m0 + tau mdot, Jacobian at
@@ -28,12 +35,73 @@ namespace {
 
 constexpr int kPx = 4;
 
-__device__ __forceinline__ uint32_t inst_slot(const float4 *__restrict__ rec, const uint32_t *__restrict__ offset,
-                                              uint32_t gi, int tx, int ty) {
-    const float4 r2 = rec[3 * (size_t)gi + 2];
+__device__ __forceinline__ uint32_t inst_slot(const float4 &r2, uint32_t off, int tx, int ty) {
     const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
     const uint32_t x0 = lo & 0xffffu, y0 = lo >> 16, x1 = hi & 0xffffu;
-    return offset[gi] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
+    return off + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
+}
+
+__device__ __forceinline__ void zero_slot(float4 *__restrict__ ig, uint32_t slot) {
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    ig[3 * (size_t)slot + 0] = z;
+    ig[3 * (size_t)slot + 1] = z;
+    ig[3 * (size_t)slot + 2] = z;
+}
+
+// Cross-lane moves within a row of 16 lanes (DPP): quad permutations [1,0,3,2] and
+// [2,3,0,1] (partner lane l ^ 1, l ^ 2) and row rotations by 4 and 8.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppRor4 = 0x124, kDppRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// v + v of lane l ^ 16, and v + v of lane l ^ 32 (row swaps).
+__device__ __forceinline__ float sum_xor16(float v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float sum_xor32(float v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Which of the eight reduce-scattered values lane l holds after wave_sum9.
+__device__ __forceinline__ int red_index(int l) { return 4 * (l & 1) + 2 * ((l >> 1) & 1) + ((l >> 2) & 1); }
+
+// Wavefront totals of nine per-lane values.  v[0..7] are reduce-scattered over the low
+// three lane bits -- at each step a lane keeps half of its values and adds its partner's
+// copy of that half (partners: l ^ 1, l ^ 2, then a rotation by 4 inside the row, which
+// pairs every lane with one of equal bits 0-1 and opposite bit 2) -- and then summed
+// over the other lanes; lane l ends with the total of v[red_index(l)] in x.  y is the
+// total of v[8].
+__device__ __forceinline__ void wave_sum9(const float v[9], float &x, float &y) {
+    const int l = lane_id();
+    const bool b0 = l & 1, b1 = (l >> 1) & 1, b2 = (l >> 2) & 1;
+    float u[4], w[2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float keep = b0 ? v[j + 4] : v[j], send = b0 ? v[j] : v[j + 4];
+        u[j] = keep + dpp_move<kDppXor1>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const float keep = b1 ? u[j + 2] : u[j], send = b1 ? u[j] : u[j + 2];
+        w[j] = keep + dpp_move<kDppXor2>(send);
+    }
+    {
+        const float keep = b2 ? w[1] : w[0], send = b2 ? w[0] : w[1];
+        x = keep + dpp_move<kDppRor4>(send);
+    }
+    x += dpp_move<kDppRor8>(x);
+    x = sum_xor32(sum_xor16(x));
+    y = v[8];
+    y += dpp_move<kDppXor1>(y);
+    y += dpp_move<kDppXor2>(y);
+    y += dpp_move<kDppRor4>(y);
+    y += dpp_move<kDppRor8>(y);
+    y = sum_xor32(sum_xor16(y));
 }
 
 __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ rec,
@@ -49,18 +117,19 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
     if (tile >= ntiles) return;
     const int tx = tile % c.TX, ty = tile / c.TX;
     const int ln = lane_id();
-    const int px = tx * kTile + (ln & 15);
+    const int lxi = ln & 15;
     const size_t plane = (size_t)c.W * c.H;
-    const float sx = (float)px + 0.5f;
-    const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + (float)(kTile - 1);
-    const float wy0 = (float)(ty * kTile) + 0.5f, wy1 = wy0 + (float)(kTile - 1);
-    float sy[kPx], Tc[kPx], S0[kPx], S1[kPx], S2[kPx], g0[kPx], g1[kPx], g2[kPx];
+    // pixel centres: (ox + 0..15, oy + 0..15)
+    const float ox = (float)(tx * kTile) + 0.5f, oy = (float)(ty * kTile) + 0.5f;
+    const float sx = ox + (float)lxi;
+    float sy[kPx], Tc[kPx], GS[kPx], g0[kPx], g1[kPx], g2[kPx];
     uint32_t nc[kPx];
     uint32_t nmax = 0;
 #pragma unroll
     for (int k = 0; k < kPx; ++k) {
-        const int py = ty * kTile + (ln >> 4) + 4 * k;
-        sy[k] = (float)py + 0.5f;
+        const int lyi = (ln >> 4) + 4 * k;
+        const int px = tx * kTile + lxi, py = ty * kTile + lyi;
+        sy[k] = oy + (float)lyi;
         const bool in = px < c.W && py < c.H;
         const size_t pi = (size_t)py * c.W + px;
         Tc[k] = in ? final_T[pi] : 1.0f;
@@ -68,113 +137,100 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
         g0[k] = in ? dL[pi] : 0.0f;
         g1[k] = in ? dL[plane + pi] : 0.0f;
         g2[k] = in ? dL[2 * plane + pi] : 0.0f;
-        S0[k] = Tc[k] * bg0;
-        S1[k] = Tc[k] * bg1;
-        S2[k] = Tc[k] * bg2;
+        GS[k] = Tc[k] * (g0[k] * bg0 + g1[k] * bg1 + g2[k] * bg2);
         nmax = max(nmax, nc[k]);
     }
     nmax = __builtin_amdgcn_readfirstlane(wave_max_u32(nmax));
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     // instances behind every pixel's last contributor get zero gradients
     for (uint32_t j = start + nmax + ln; j < end; j += kWave) {
-        const uint32_t slot = inst_slot(rec, offset, vals[j], tx, ty);
-        if (slot >= capacity) continue;  // only after an instance overflow
-        ig[3 * (size_t)slot + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
-        ig[3 * (size_t)slot + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        ig[3 * (size_t)slot + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        const uint32_t gi = vals[j];
+        const uint32_t slot = inst_slot(rec[3 * (size_t)gi + 2], offset[gi], tx, ty);
+        if (slot < capacity) zero_slot(ig, slot);  // false only after an instance overflow
     }
+    // s2 = {b, bits(list position), bits(slot), amax}, s3 = {conic a, b, c, -}
     __shared__ float4 s0[kWave], s1[kWave], s2[kWave], s3[kWave];
+    __shared__ float red[kWave * 9];
+    const float wx1 = ox + (float)(kTile - 1), wy1 = oy + (float)(kTile - 1);
     // batches of 64 list entries, last batch first
     for (uint32_t jb = start + nmax; jb > start;) {
         const uint32_t j0 = jb - start > (uint32_t)kWave ? jb - kWave : start;
         const uint32_t j = j0 + ln;
+        bool keep = false;
+        float4 f0, f1, f2, r0, r1;
+        uint32_t slot = 0;
         if (j < jb) {
             const uint32_t gi = vals[j];
-            float4 f0, f1, f2;
-            fold_splat(rec, gi, f0, f1, f2);
-            s0[ln] = f0;
-            s1[ln] = f1;
-            s2[ln] = f2;
-            const float4 r0 = rec[3 * (size_t)gi + 0];
-            const float cC = rec[3 * (size_t)gi + 1].x;
-            s3[ln] = make_float4(r0.z, r0.w, cC, __uint_as_float(inst_slot(rec, offset, gi, tx, ty)));
+            r0 = rec[3 * (size_t)gi + 0];
+            r1 = rec[3 * (size_t)gi + 1];
+            const float4 r2 = rec[3 * (size_t)gi + 2];
+            fold_raw(r0, r1, r2, f0, f1, f2);
+            slot = inst_slot(r2, offset[gi], tx, ty);
+            keep = !splat_misses(f0, f2, ox, wx1, oy, wy1);
+            if (!keep && slot < capacity) zero_slot(ig, slot);  // no pixel of the tile reaches 1/255
+        }
+        const uint64_t km = __ballot(keep);
+        if (keep) {
+            const int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+            s0[pos] = f0;
+            s1[pos] = f1;
+            s2[pos] = make_float4(f2.x, __uint_as_float(j - start), __uint_as_float(slot), r1.y);
+            s3[pos] = make_float4(r0.z, r0.w, r1.x, 0.0f);
         }
         __syncthreads();
-        for (int i = (int)(jb - j0) - 1; i >= 0; --i) {
-            const float4 f0 = s0[i], f1 = s1[i], f2 = s2[i], f3 = s3[i];
-            const uint32_t jj = j0 - start + (uint32_t)i;  // position in the tile's list
-            if (__builtin_amdgcn_readfirstlane((int)splat_misses(f0, f2, wx0, wx1, wy0, wy1))) {
-                // no pixel of the tile can reach alpha >= 1/255: zero gradient
-                const uint32_t slot = __float_as_uint(f3.w);
-                if (ln == 0 && slot < capacity) {
-                    ig[3 * (size_t)slot + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    ig[3 * (size_t)slot + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    ig[3 * (size_t)slot + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-                continue;
-            }
-            const float dx = sx - f0.x;
-            const ColTerms ct = col_terms(f0, f1, dx);
-            const float amax = f2.y;
-            const float cA = f3.x, cB = f3.y, cC = f3.z;
-            float a_mx = 0.f, a_my = 0.f, a_A = 0.f, a_B = 0.f, a_C = 0.f, a_am = 0.f, a_r = 0.f, a_g = 0.f,
-                  a_b = 0.f;
-            bool any = false;
+        const int nb = __popcll(km);
+        for (int i = nb - 1; i >= 0; --i) {
+            const float4 h0 = s0[i], h1 = s1[i];
+            const float2 h2 = *reinterpret_cast<const float2 *>(&s2[i]);
+            const uint32_t jj = __float_as_uint(h2.y);  // position in the tile's list
+            const float dx = sx - h0.x;
+            const ColTerms ct = col_terms(h0, h1, dx);
+            float d0 = 0.f, e1 = 0.f, e2 = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
 #pragma unroll
             for (int k = 0; k < kPx; ++k) {
-                const float dy = sy[k] - f0.y;
-                const float q = pix_exponent(ct, f1, dy);
+                const float dy = sy[k] - h0.y;
+                const float q = pix_exponent(ct, h1, dy);
                 const float e = exp2_fast(q);
                 const float alpha = fminf(kAlphaMax, e);
-                const bool ok = jj < nc[k] && !(q > f1.y) && alpha >= kAlphaMin;
-                if (ok) {
-                    any = true;
-                    const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-                    const float Ti = Tc[k] * inv;  // transmittance in front of this splat
-                    const float da = g0[k] * (f1.z * Ti - S0[k] * inv) + g1[k] * (f1.w * Ti - S1[k] * inv) +
-                                     g2[k] * (f2.x * Ti - S2[k] * inv);
-                    const float wgt = alpha * Ti;
-                    a_r += g0[k] * wgt;
-                    a_g += g1[k] * wgt;
-                    a_b += g2[k] * wgt;
-                    S0[k] += f1.z * wgt;
-                    S1[k] += f1.w * wgt;
-                    S2[k] += f2.x * wgt;
-                    Tc[k] = Ti;
-                    if (e <= kAlphaMax) {  // not clamped: alpha = amax * exp(power)
-                        const float dp = da * alpha;  // d/d(power)
-                        a_am += da * (e * __builtin_amdgcn_rcpf(amax));
-                        a_mx += dp * (cA * dx + cB * dy);
-                        a_my += dp * (cC * dy + cB * dx);
-                        a_A += dp * (-0.5f * dx * dx);
-                        a_B += dp * (-(dx * dy));
-                        a_C += dp * (-0.5f * dy * dy);
-                    }
-                }
+                const uint64_t ok = __ballot(jj < nc[k]) & __ballot(!(q > h1.y)) & __ballot(alpha >= kAlphaMin);
+                const bool okb = __builtin_amdgcn_inverse_ballot_w64(ok);
+                const bool unclamped = __builtin_amdgcn_inverse_ballot_w64(ok & __ballot(e <= kAlphaMax));
+                const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                const float Ti = Tc[k] * inv;  // transmittance in front of this splat
+                const float gc = __builtin_fmaf(g2[k], h2.x, __builtin_fmaf(g1[k], h1.w, g0[k] * h1.z));
+                const float wgt = okb ? alpha * Ti : 0.0f;
+                const float da = __builtin_fmaf(-inv, GS[k], Ti * gc);
+                GS[k] = __builtin_fmaf(gc, wgt, GS[k]);
+                ar = __builtin_fmaf(g0[k], wgt, ar);
+                ag = __builtin_fmaf(g1[k], wgt, ag);
+                ab = __builtin_fmaf(g2[k], wgt, ab);
+                Tc[k] = okb ? Ti : Tc[k];
+                // d/d(power); zero where alpha is clamped (alpha = amax exp(power) otherwise)
+                const float dp = unclamped ? da * alpha : 0.0f;
+                const float dpdy = dp * dy;
+                d0 += dp;
+                e1 += dpdy;
+                e2 = __builtin_fmaf(dpdy, dy, e2);
             }
-            const uint32_t slot = __float_as_uint(f3.w);
-            const bool slot_ok = slot < capacity;  // false only after an instance overflow
-            if (__ballot(any) == 0) {
-                if (ln == 0 && slot_ok) {
-                    ig[3 * (size_t)slot + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    ig[3 * (size_t)slot + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    ig[3 * (size_t)slot + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-                continue;
-            }
-            a_mx = wave_sum(a_mx);
-            a_my = wave_sum(a_my);
-            a_A = wave_sum(a_A);
-            a_B = wave_sum(a_B);
-            a_C = wave_sum(a_C);
-            a_am = wave_sum(a_am);
-            a_r = wave_sum(a_r);
-            a_g = wave_sum(a_g);
-            a_b = wave_sum(a_b);
-            if (ln == 0 && slot_ok) {
-                ig[3 * (size_t)slot + 0] = make_float4(a_mx, a_my, a_A, a_B);
-                ig[3 * (size_t)slot + 1] = make_float4(a_C, a_am, a_r, a_g);
-                ig[3 * (size_t)slot + 2] = make_float4(a_b, 0.f, 0.f, 0.f);
+            const float v[9] = {d0, dx * d0, e1, (dx * dx) * d0, dx * e1, e2, ar, ag, ab};
+            float x, y;
+            wave_sum9(v, x, y);
+            if (ln < 9) red[9 * i + (ln < 8 ? red_index(ln) : 8)] = ln < 8 ? x : y;
+        }
+        __syncthreads();
+        // one lane per kept splat: moments -> gradients of the 2D mean (d power / d m =
+        // Q d), the conic (-d d^T / 2, off-diagonal -dx dy) and amax (alpha / amax per
+        // unclamped pixel)
+        if (ln < nb) {
+            const float *m = &red[9 * ln];
+            const float P0 = m[0], Sx = m[1], Sy = m[2], Sxx = m[3], Sxy = m[4], Syy = m[5];
+            const float4 h2 = s2[ln], h3 = s3[ln];
+            const uint32_t sl = __float_as_uint(h2.z);
+            if (sl < capacity) {
+                ig[3 * (size_t)sl + 0] = make_float4(h3.x * Sx + h3.y * Sy, h3.z * Sy + h3.y * Sx, -0.5f * Sxx, -Sxy);
+                ig[3 * (size_t)sl + 1] = make_float4(-0.5f * Syy, P0 / h2.w, m[6], m[7]);
+                ig[3 * (size_t)sl + 2] = make_float4(m[8], 0.f, 0.f, 0.f);
             }
         }
         __syncthreads();
