@@ -18,11 +18,11 @@
 //                    depend on the order the atomics handed out positions.  Buckets of up to
 //                    kRankMax keys are sorted by ranking: the keys are unique, so a key's
 //                    sorted position is the number of smaller keys, counted by each thread
-//                    for its own keys against the bucket broadcast from LDS.  Up to kLdsSort
-//                    keys: bitonic network in LDS; larger: stable least-significant-digit
-//                    radix sort over the 64 key bits, 8-bit digits, ping-ponging in global
-//                    scratch.  Writes keys = (tile << 32) | float-bits(depth) and
-//                    values = gaussian.
+//                    for its own (up to two) keys while the wavefront streams the bucket
+//                    through scalar loads -- no LDS, no barriers.  Larger buckets: stable
+//                    least-significant-digit radix sort over the 64 key bits, 8-bit digits,
+//                    ping-ponging between two global scratch arrays.  Writes
+//                    keys = (tile << 32) | float-bits(depth) and values = gaussian.
 //
 // The instance total lives on the device; no host synchronisation is needed.  If it
 // exceeds the capacity, a status word is set and every later stage does nothing.
@@ -35,7 +35,6 @@ namespace {
 constexpr int kScanThreads = 1024;
 constexpr int kSortThreads = 256;
 constexpr int kRankMax = 2 * kSortThreads;  // largest bucket sorted by ranking (two keys per thread)
-constexpr int kLdsSort = 2048;              // largest bucket sorted by a bitonic network in LDS
 static_assert(kSortThreads == kBlock && kSortThreads == kRadix, "one digit counter per thread");
 
 __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *tmp4) {
@@ -237,15 +236,19 @@ __device__ __forceinline__ void write_out(uint64_t k, uint32_t pos, uint32_t til
     vals[pos] = (uint32_t)k;
 }
 
-// Stable LSD radix sort of src[0, s) by all 64 key bits, one workgroup of kSortThreads,
-// 8-bit digits, ping-ponging between src and alt; returns the buffer holding the result.
-// Elements are ranked in chunks of kSortThreads: within a wavefront by ballot matching on
-// the digit bits, across the wavefronts of the chunk by per-wave digit counts in LDS.
-__device__ uint64_t *block_radix_sort(uint64_t *src, uint64_t *alt, uint32_t s, uint32_t *cnt /* [kRadix] */,
-                                      uint32_t *wc /* [kSortThreads / kWave][kRadix] */, uint32_t *tmp4) {
+// Stable LSD radix sort of src0[0, s) by all 64 key bits, one workgroup of kSortThreads,
+// 8-bit digits: pass 1 reads src0 and writes a, later passes alternate a -> b -> a, so the
+// eighth pass leaves the result in b.  Elements are ranked in chunks of kSortThreads:
+// within a wavefront by ballot matching on the digit bits, across the wavefronts of the
+// chunk by per-wave digit counts in LDS.
+__device__ void block_radix_sort(const uint64_t *src0, uint64_t *a, uint64_t *b, uint32_t s,
+                                 uint32_t *cnt /* [kRadix] */, uint32_t *wc /* [kSortThreads / kWave][kRadix] */,
+                                 uint32_t *tmp4) {
     constexpr int NW = kSortThreads / kWave;
     const int tid = threadIdx.x, w = tid / kWave;
     const uint64_t lt = lanemask_lt();
+    const uint64_t *src = src0;
+    uint64_t *dst = a;
     for (int shift = 0; shift < 64; shift += 8) {
         cnt[tid] = 0u;
         __syncthreads();
@@ -264,8 +267,8 @@ __device__ uint64_t *block_radix_sort(uint64_t *src, uint64_t *alt, uint32_t s, 
             const uint32_t d = (uint32_t)(k >> shift) & 0xffu;
             uint64_t peers = __ballot(valid);
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const bool bit = (d >> b) & 1u;
+            for (int bt = 0; bt < 8; ++bt) {
+                const bool bit = (d >> bt) & 1u;
                 const uint64_t bb = __ballot(bit);
                 peers &= bit ? bb : ~bb;
             }
@@ -275,29 +278,50 @@ __device__ uint64_t *block_radix_sort(uint64_t *src, uint64_t *alt, uint32_t s, 
             uint32_t before = 0, total = 0;
 #pragma unroll
             for (int q = 0; q < NW; ++q) before += q < w ? wc[q * kRadix + d] : 0u;
-            if (valid) alt[cnt[d] + before + rank] = k;
+            if (valid) dst[cnt[d] + before + rank] = k;
 #pragma unroll
             for (int q = 0; q < NW; ++q) total += wc[q * kRadix + tid];
             __syncthreads();
             cnt[tid] += total;
         }
         __syncthreads();
-        uint64_t *t = src;
-        src = alt;
-        alt = t;
+        src = dst;
+        dst = dst == a ? b : a;
     }
-    return src;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_tile_sort(uint64_t *__restrict__ bucket,
+// Number of keys of b[0, s) below k0 and below k1 (the bucket is read with wave-uniform
+// addresses, i.e. scalar loads).
+template <bool TWO>
+__device__ __forceinline__ void rank2(const uint64_t *__restrict__ b, uint32_t s, uint64_t k0, uint64_t k1,
+                                      uint32_t &r0, uint32_t &r1) {
+    uint32_t j = 0;
+    for (; j + 16 <= s; j += 16) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const uint64_t kj = b[j + q];
+            r0 += kj < k0;
+            if (TWO) r1 += kj < k1;
+        }
+    }
+    for (; j < s; ++j) {
+        const uint64_t kj = b[j];
+        r0 += kj < k0;
+        if (TWO) r1 += kj < k1;
+    }
+}
+
+// The bucket is only read here (the radix sort ping-pongs between alt and the key
+// output), so its wave-uniform loads can go through the scalar cache.
+__global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint64_t *__restrict__ bucket,
                                                             uint64_t *__restrict__ alt,
                                                             const uint32_t *__restrict__ ranges, int tiles,
                                                             uint64_t *__restrict__ keys,
                                                             uint32_t *__restrict__ vals,
                                                             const uint32_t *__restrict__ misc) {
     if (misc[1] != 0u) return;
-    __shared__ __align__(16) uint64_t sk[kLdsSort];
     __shared__ uint32_t cnt[kRadix];
+    __shared__ uint32_t wc[(kSortThreads / kWave) * kRadix];
     __shared__ uint32_t tmp4[kSortThreads / kWave];
     const int tile = blockIdx.x;
     if (tile >= tiles) return;
@@ -306,60 +330,24 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(uint64_t *__restrict
     const uint32_t tid = threadIdx.x;
     if (s == 0) return;
     if (s <= (uint32_t)kRankMax) {
+        if ((tid & ~(uint32_t)(kWave - 1)) >= s) return;  // a wavefront without keys
         const uint32_t i1 = tid + kSortThreads;
         const uint64_t k0 = tid < s ? bucket[start + tid] : ~0ull;
         const uint64_t k1 = i1 < s ? bucket[start + i1] : ~0ull;
-        // padded to a multiple of 4 with the largest key (never below a real key)
-        const uint32_t s4 = (s + 3u) & ~3u;
-        if (tid < s4) sk[tid] = k0;
-        if (i1 < s4) sk[i1] = k1;
-        __syncthreads();
-        if ((tid & ~(uint32_t)(kWave - 1)) >= s) return;  // a wavefront without keys
-        const ulonglong2 *sk2 = reinterpret_cast<const ulonglong2 *>(sk);
         uint32_t r0 = 0, r1 = 0;
-        if (s <= (uint32_t)kSortThreads) {
-            for (uint32_t j = 0; j < s4 / 2; j += 2) {
-                const ulonglong2 a = sk2[j], b = sk2[j + 1];
-                r0 += (a.x < k0) + (a.y < k0) + (b.x < k0) + (b.y < k0);
-            }
-        } else {
-            for (uint32_t j = 0; j < s4 / 2; j += 2) {
-                const ulonglong2 a = sk2[j], b = sk2[j + 1];
-                r0 += (a.x < k0) + (a.y < k0) + (b.x < k0) + (b.y < k0);
-                r1 += (a.x < k1) + (a.y < k1) + (b.x < k1) + (b.y < k1);
-            }
-        }
+        if (s <= (uint32_t)kSortThreads)
+            rank2<false>(bucket + start, s, k0, k1, r0, r1);
+        else
+            rank2<true>(bucket + start, s, k0, k1, r0, r1);
         if (tid < s) write_out(k0, start + r0, (uint32_t)tile, keys, vals);
         if (i1 < s) write_out(k1, start + r1, (uint32_t)tile, keys, vals);
         return;
     }
-    if (s <= (uint32_t)kLdsSort) {
-        uint32_t P = 2 * kRankMax;
-        while (P < s) P <<= 1;
-        for (uint32_t i = tid; i < P; i += kSortThreads) sk[i] = i < s ? bucket[start + i] : ~0ull;
-        __syncthreads();
-        for (uint32_t size = 2; size <= P; size <<= 1) {
-            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t p = tid; p < P / 2; p += kSortThreads) {
-                    const uint32_t i = 2 * p - (p & (stride - 1));  // lower index of the pair
-                    const uint32_t j = i + stride;
-                    const bool up = (i & size) == 0;
-                    const uint64_t a = sk[i], b = sk[j];
-                    if ((a > b) == up) {
-                        sk[i] = b;
-                        sk[j] = a;
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (uint32_t i = tid; i < s; i += kSortThreads) write_out(sk[i], start + i, (uint32_t)tile, keys, vals);
-        return;
-    }
-    // large bucket: radix sort in global scratch (same index range of `alt`); the digit
-    // counts per wavefront reuse the LDS of the bitonic path
-    uint64_t *res = block_radix_sort(bucket + start, alt + start, s, cnt, reinterpret_cast<uint32_t *>(sk), tmp4);
-    for (uint32_t i = tid; i < s; i += kSortThreads) write_out(res[i], start + i, (uint32_t)tile, keys, vals);
+    // large bucket: 8 radix passes bucket -> alt -> keys -> alt ... -> keys (same index
+    // range of each); the last pass leaves the sorted bucket in keys, which write_out
+    // then rewrites in place, element by element
+    block_radix_sort(bucket + start, alt + start, keys + start, s, cnt, wc, tmp4);
+    for (uint32_t i = tid; i < s; i += kSortThreads) write_out(keys[start + i], start + i, (uint32_t)tile, keys, vals);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -408,7 +396,7 @@ hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *o
     if (nb > 0)
         hipLaunchKernelGGL(k_emit<false>, dim3(nb), dim3(kBlock), 0, st, rec, count, partial, offset, n, c.TX,
                            ws.misc, ws.tcnt, ws.grp_off, ws.inst_off, ws.bucket);
-    hipLaunchKernelGGL(k_tile_sort, dim3(tiles), dim3(kSortThreads), 0, st, ws.bucket, ws.alt, ranges, tiles, keys, vals,
+    hipLaunchKernelGGL(k_tile_sort, dim3(tiles), dim3(kSortThreads), 0, st, (const uint64_t *)ws.bucket, ws.alt, ranges, tiles, keys, vals,
                        ws.misc);
     return hipGetLastError();
 }

@@ -221,34 +221,69 @@ def render(mean, scale, quat, opacity, t_mean, t_scale, velocity, sh, *, cam, t,
 
 class Renderer:
     """Fixed device buffers for repeated frames of one resolution (timing loops,
-    sweeps).  Fully asynchronous: no host synchronisation per frame."""
+    sweeps).  Fully asynchronous: no host synchronisation per frame.  The argument
+    structs of the three entry points are built once (camera structs once per camera
+    object: cameras passed here are treated as immutable), so a frame costs three
+    foreign calls on the host."""
 
     def __init__(self, scene: DeviceScene, width, height, capacity=None, cache=True, keep_state=False):
         self.scene = scene
         self.width, self.height = int(width), int(height)
+        dev = scene.t["mean"].device
         self.st = FrameState(scene.n, self.width, self.height,
-                             capacity or default_capacity(scene.n, width, height), scene.t["mean"].device)
-        self.cache = CamCache(scene.n, scene.t["mean"].device) if cache else None
+                             capacity or default_capacity(scene.n, width, height), dev)
+        self.cache = CamCache(scene.n, dev) if cache else None
         self.keep_state = keep_state
-        self.img = torch.empty((3, self.height, self.width), dtype=torch.float32, device=scene.t["mean"].device)
-
-    def render(self, cam, t, bg=(0.0, 0.0, 0.0)):
-        assert cam.width == self.width and cam.height == self.height
-        project(self.scene, cam, t, self.st, self.cache)
-        bin_sort(self.st)
-        return self.blend(bg)
-
-    def blend(self, bg=(0.0, 0.0, 0.0)):
-        if self.keep_state and self.st.final_T is None:
-            dev = self.img.device
+        self.img = torch.empty((3, self.height, self.width), dtype=torch.float32, device=dev)
+        if keep_state:
             self.st.final_T = torch.empty((self.height, self.width), dtype=torch.float32, device=dev)
             self.st.n_contrib = torch.empty((self.height, self.width), dtype=torch.int32, device=dev)
         st = self.st
-        sp, bn = st.splats(), st.bins()
-        B.check(B.lib.d4dgs_render_fwd(C.byref(sp), C.byref(bn), self.width, self.height, C.byref(_bg(bg)),
-                                       _ptr(self.img), _ptr(st.final_T) if self.keep_state else None,
-                                       _ptr(st.n_contrib) if self.keep_state else None, _stream()))
+        self._scene_s = scene.struct()
+        self._sp = st.splats()
+        self._bn = st.bins()
+        self._cache_p = C.byref(self.cache.c) if cache else None
+        self._ws = (_ptr(st.ws), st.ws.numel())
+        self._status = _ptr(st.status)
+        self._img = _ptr(self.img)
+        self._state = (_ptr(st.final_T), _ptr(st.n_contrib)) if keep_state else (None, None)
+        self._cams = {}
+        self._bgs = {}
+
+    def _cam(self, cam):
+        hit = self._cams.get(id(cam))
+        if hit is None or hit[0] is not cam:
+            hit = (cam, B.camera_struct(cam))
+            self._cams[id(cam)] = hit
+        return hit[1]
+
+    def _bg(self, bg):
+        key = tuple(float(x) for x in bg)
+        a = self._bgs.get(key)
+        if a is None:
+            a = self._bgs[key] = _bg(key)
+        return a
+
+    def project(self, cam, t, stream=None):
+        assert cam.width == self.width and cam.height == self.height
+        B.check(B.lib.d4dgs_project(C.byref(self._scene_s), C.byref(self._cam(cam)), float(t), self._cache_p,
+                                    C.byref(self._sp), stream or _stream()))
+
+    def bin_sort(self, stream=None):
+        B.check(B.lib.d4dgs_bin_sort(C.byref(self._sp), self.st.n, self.width, self.height, self._ws[0],
+                                     self._ws[1], C.byref(self._bn), self._status, stream or _stream()))
+
+    def blend(self, bg=(0.0, 0.0, 0.0), stream=None):
+        B.check(B.lib.d4dgs_render_fwd(C.byref(self._sp), C.byref(self._bn), self.width, self.height,
+                                       C.byref(self._bg(bg)), self._img, self._state[0], self._state[1],
+                                       stream or _stream()))
         return self.img
+
+    def render(self, cam, t, bg=(0.0, 0.0, 0.0)):
+        stream = _stream()
+        self.project(cam, t, stream)
+        self.bin_sort(stream)
+        return self.blend(bg, stream)
 
     def backward(self, cam, t, dL_dimg, grads, bg=(0.0, 0.0, 0.0)):
         """Adjoint of the last render() (needs keep_state=True); adds into grads."""
