@@ -29,10 +29,20 @@ if ROOT not in sys.path:
 FRAMES_PER_STEP = 300
 # Blend roofline.  Algorithmic work per (pixel, splat) evaluation of Eq. 4, counted on
 # the definition: exponent -1/2(a dx^2 + c dy^2) - b dx dy (11 flops), exp (1),
-# alpha = amax G (1), T' = T (1 - alpha) (2), C += c alpha T (7)  ->  22 flops.
+# alpha = amax G (1), T' = T (1 - alpha) (2), C += c alpha T (7)  ->  22 flops.  The
+# evaluations are the oracle's exact count E (every pixel over its tile list up to its
+# stop); the kernel skips many of them (splats whose alpha >= 1/255 box misses a
+# wavefront's pixels), so this is an effective rate.
 FLOPS_PER_EVAL = 22
-# FP32 vector peak without packed math: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz.
-ALU_PEAK_TFLOPS = 78.6
+# FP32 vector peak of MI355X: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 157.3
+# The same without packed FP32 (the issue-slot bound of the code as compiled).
+ALU_PEAK_NONPACKED_TFLOPS = 78.6
+# HBM bytes per blend launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters, valid only
+# while the blend's sources are the ones the counters were taken with.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_blend_pmc_traffic_300k_1352x1014.txt")
+BLEND_SOURCES = ("paper_2503_22159_amd/csrc/blend.hip", "paper_2503_22159_amd/csrc/internal.hpp",
+                 "paper_2503_22159_amd/build.py")
 
 
 def parse():
@@ -44,10 +54,49 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=10)
+    ap.add_argument("--cpu-frames", type=int, default=100)
     ap.add_argument("--bwd-frames", type=int, default=20)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 256 MiB buffer three times (the reference kernel for scaling "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
     return ap.parse_args()
+
+
+def blend_sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in BLEND_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def blend_traffic():
+    """HBM bytes per blend launch from the committed counter summary, or None when there
+    is none or the blend's sources have changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        if kv.get("sources_sha256") != blend_sources_sha256():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    import torch
+
+    n = 64 << 20  # 256 MiB of float32
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"copy calibration: 3 copies of {4 * n} bytes", file=sys.stderr, flush=True)
 
 
 def sweep(args, ds, cams, times, render):
@@ -122,8 +171,8 @@ def cpu_baseline(args, scene, cams, times):
 
     oracle.build(force=False)
     n = args.cpu_frames
-    idx = [(j * len(cams)) // n for j in range(n)]
-    sample = [(cams[j], times[(j * 37) % len(times)]) for j in idx]
+    # frame j: camera j mod 20 at time index 37 j mod 300 -- spread over the whole sweep
+    sample = [(cams[j % len(cams)], times[(37 * j) % len(times)]) for j in range(n)]
     evals = []
     t0 = time.perf_counter()
     for cam, t in sample:
@@ -131,8 +180,8 @@ def cpu_baseline(args, scene, cams, times):
         evals.append(res["n_eval"])
     el = time.perf_counter() - t0
     base = {"value": round(n / el, 4), "unit": "frames/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n} frames of the timed sweep (cameras {idx[0]}..{idx[-1]} step {idx[1] - idx[0]}, "
-                      f"t spread over [0,1]); project + bin + blend per frame"}
+            "sample": f"{n} frames of the timed sweep (frame j: camera j mod {len(cams)}, time index "
+                      f"37 j mod {len(times)}); project + bin + blend per frame, {el:.1f} s"}
     return base, sum(evals) / len(evals)
 
 
@@ -149,6 +198,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
     scene = inputs.config2_scene()
     ds = render.DeviceScene.from_inputs(scene)
     cams = inputs.config2_cameras()
@@ -191,8 +242,9 @@ def main():
         achieved = mean_evals * FLOPS_PER_EVAL / (blend_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "kernel": "k_blend", "achieved": round(achieved, 3),
                            "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                           "traffic": None, "evals_per_frame": int(mean_evals),
-                           "flops_per_eval": FLOPS_PER_EVAL}
+                           "traffic": blend_traffic(), "evals_per_frame": int(mean_evals),
+                           "flops_per_eval": FLOPS_PER_EVAL, "peak_nonpacked": ALU_PEAK_NONPACKED_TFLOPS,
+                           "frac_nonpacked": round(achieved / ALU_PEAK_NONPACKED_TFLOPS, 4)}
     print(json.dumps(out), flush=True)
 
 
