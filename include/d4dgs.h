@@ -169,10 +169,14 @@ d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, fl
 
 /* Tile binning and depth sort of the projected splats (the 3DGS tiled rasteriser the
  * paper uses, Sec. 3.2.2): exclusive scan of counts into splats->offset, emission of
- * (tile, depth) keys for every tile of each splat's rectangle, stable LSD radix sort,
- * per-tile ranges.  If the instance total exceeds bins->capacity, *d_status (device
- * int32, may be NULL) is set to D4DGS_ERR_CAPACITY and only the first capacity
- * instances are kept.  workspace: d4dgs_workspace_size bytes (device). */
+ * every (tile, splat) instance of each splat's rectangle into per-tile buckets, a sort
+ * of each bucket by (float-bits(depth), Gaussian index), per-tile ranges.  The output
+ * is the ascending order of the 64-bit keys (tile << 32) | float-bits(depth) with ties
+ * by index.  If the instance total exceeds bins->capacity, *d_status (device int32,
+ * may be NULL) is set to D4DGS_ERR_CAPACITY, *num_instances still receives the total,
+ * nothing is emitted and every range is empty (a render of such bins shows only the
+ * background).  workspace: d4dgs_workspace_size bytes (device); it needs no
+ * initialisation. */
 d4dgs_status d4dgs_bin_sort(const d4dgs_splats *splats, int32_t n, int32_t width, int32_t height,
                             void *workspace, size_t workspace_bytes, d4dgs_bins *bins,
                             int32_t *d_status, d4dgs_stream stream);
