@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=FRAMES_PER_STEP, help="frames per step (times per camera)")
+    ap.add_argument("--streams", type=int, default=3, help="HIP streams the sweep's frames alternate over")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -100,29 +101,39 @@ def copy_calibration():
 
 
 def sweep(args, ds, cams, times, render):
-    """The timed camera-major sweep; HIP events (created beforehand) bracket every blend
-    launch on the stream the frames are enqueued on."""
+    """The timed camera-major sweep.  Frames are independent, so consecutive frames go
+    round-robin to `--streams` HIP streams (default priority), each with its own frame
+    buffers and camera-stage cache: one frame's binning overlaps another's blend.  HIP
+    events (created and first recorded beforehand) bracket every blend launch on the
+    stream it is launched on."""
     import torch
 
     W, H = cams[0].width, cams[0].height
-    rend = render.Renderer(ds, W, H, capacity=4 * ds.n, cache=True)
-    stream = render._stream()
+    S = max(1, args.streams)
+    rends = [render.Renderer(ds, W, H, capacity=4 * ds.n, cache=True) for _ in range(S)]
+    streams = [torch.cuda.Stream() for _ in range(S)]
+    handles = [st.cuda_stream for st in streams]
     nfr = len(times)
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps * nfr)]
+    for i, (e0, e1) in enumerate(events):  # materialise the events outside the timed region
+        e0.record(streams[i % S])
+        e1.record(streams[i % S])
 
     def step(k, ev):
         cam = cams[k % len(cams)]
         for i, t in enumerate(times):
-            rend.project(cam, t, stream)
-            rend.bin_sort(stream)
+            r = i % S
+            rend, h = rends[r], handles[r]
+            rend.project(cam, t, h)
+            rend.bin_sort(h)
             if ev is not None:
                 e0, e1 = ev[i]
-                e0.record()
-                rend.blend(stream=stream)
-                e1.record()
+                e0.record(streams[r])
+                rend.blend(stream=h)
+                e1.record(streams[r])
             else:
-                rend.blend(stream=stream)
+                rend.blend(stream=h)
 
     for k in range(args.warmup):
         step(len(cams) - 1 - k, None)
@@ -133,7 +144,7 @@ def sweep(args, ds, cams, times, render):
     t_host = time.perf_counter() - t0
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    assert not rend.overflowed(), "instance capacity exceeded during the sweep"
+    assert not any(r.overflowed() for r in rends), "instance capacity exceeded during the sweep"
     blend_ms = [a.elapsed_time(b) for a, b in events]
     return elapsed, sum(blend_ms) / len(blend_ms), t_host
 
@@ -222,7 +233,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "300k Gaussians (SH3, 32 clusters), 1352x1014, 20-camera arc x 300 times, "
-                               "camera-stage cache on", "frames_per_step": args.frames,
+                               "camera-stage cache on", "frames_per_step": args.frames, "streams": args.streams,
                    "gaussians": scene.n, "width": W, "height": H},
         "blend_ms_avg": round(blend_ms, 5),
         "host_enqueue_ms_per_frame": round(1000.0 * t_host / frames, 5),
