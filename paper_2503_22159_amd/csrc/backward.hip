@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
         const uint32_t slot = inst_slot(rec[3 * (size_t)gi + 2], offset[gi], tx, ty);
         if (slot < capacity) zero_slot(ig, slot);  // false only after an instance overflow
     }
-    // s2 = {b, bits(list position), bits(slot), amax}, s3 = {conic a, b, c, -}
+    // s2 = {b, bits(plain << 31 | list position), bits(slot), amax}, s3 = {conic a, b, c, -}
     __shared__ float4 s0[kWave], s1[kWave], s2[kWave], s3[kWave];
     __shared__ float red[kWave * 9];
     const float wx1 = ox + (float)(kTile - 1), wy1 = oy + (float)(kTile - 1);
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
     for (uint32_t jb = start + nmax; jb > start;) {
         const uint32_t j0 = jb - start > (uint32_t)kWave ? jb - kWave : start;
         const uint32_t j = j0 + ln;
-        bool keep = false;
+        bool keep = false, plain = false;
         float4 f0, f1, f2, r0, r1;
         uint32_t slot = 0;
         if (j < jb) {
@@ -167,6 +167,7 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
             fold_raw(r0, r1, r2, f0, f1, f2);
             slot = inst_slot(r2, offset[gi], tx, ty);
             keep = !splat_misses(f0, f2, ox, wx1, oy, wy1);
+            plain = splat_plain(r0, r1);
             if (!keep && slot < capacity) zero_slot(ig, slot);  // no pixel of the tile reaches 1/255
         }
         const uint64_t km = __ballot(keep);
@@ -175,7 +176,8 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
             s0[pos] = f0;
             s1[pos] = f1;
-            s2[pos] = make_float4(f2.x, __uint_as_float(j - start), __uint_as_float(slot), r1.y);
+            s2[pos] = make_float4(f2.x, __uint_as_float((plain ? 0x80000000u : 0u) | (j - start)),
+                                  __uint_as_float(slot), r1.y);
             s3[pos] = make_float4(r0.z, r0.w, r1.x, 0.0f);
         }
         __syncthreads();
@@ -183,7 +185,10 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
         for (int i = nb - 1; i >= 0; --i) {
             const float4 h0 = s0[i], h1 = s1[i];
             const float2 h2 = *reinterpret_cast<const float2 *>(&s2[i]);
-            const uint32_t jj = __float_as_uint(h2.y);  // position in the tile's list
+            const uint32_t tag = __builtin_amdgcn_readfirstlane(__float_as_uint(h2.y));
+            const uint32_t jj = tag & 0x7fffffffu;  // position in the tile's list
+            // the forward's per-splat tests: no "exponent > 0" skip for plain splats
+            const uint64_t pos_ok = (tag >> 31) ? ~0ull : 0ull;
             const float dx = sx - h0.x;
             const ColTerms ct = col_terms(h0, h1, dx);
             float d0 = 0.f, e1 = 0.f, e2 = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
@@ -193,7 +198,8 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
                 const float q = pix_exponent(ct, h1, dy);
                 const float e = exp2_fast(q);
                 const float alpha = fminf(kAlphaMax, e);
-                const uint64_t ok = __ballot(jj < nc[k]) & __ballot(!(q > h1.y)) & __ballot(alpha >= kAlphaMin);
+                const uint64_t ok =
+                    __ballot(jj < nc[k]) & (pos_ok | __ballot(!(q > h1.y))) & __ballot(alpha >= kAlphaMin);
                 const bool okb = __builtin_amdgcn_inverse_ballot_w64(ok);
                 const bool unclamped = __builtin_amdgcn_inverse_ballot_w64(ok & __ballot(e <= kAlphaMax));
                 const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);

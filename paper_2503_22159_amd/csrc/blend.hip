@@ -29,6 +29,39 @@ namespace {
 // Staging culls: each lane tests its own splat's alpha >= 1/255 box against the wavefront's
 // pixel-centre box and only the splats that can reach one of its pixels are parked, compacted
 // in list order (ballot + lane-rank), so the per-splat loop carries no test.
+// One splat against the lane's PX pixels.  PLAIN: the splat passed splat_plain, so the
+// "exponent > 0" skip and the 0.99 clamp cannot fire and are not evaluated.  Returns true
+// when every pixel of the wavefront is done.
+template <int PX, bool STATE, bool PLAIN>
+__device__ __forceinline__ bool blend_splat(const float4 &g0, const float4 &g1, float cb, uint32_t pos, float sx,
+                                            const float (&sy)[PX], float (&T)[PX], float (&C0)[PX],
+                                            float (&C1)[PX], float (&C2)[PX], uint64_t (&done)[PX],
+                                            uint32_t (&last)[PX]) {
+    const ColTerms ct = col_terms(g0, g1, sx - g0.x);
+    uint64_t all = ~0ull;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+        const float q = pix_exponent(ct, g1, sy[k] - g0.y);
+        const float e = exp2_fast(q);
+        const float alpha = PLAIN ? e : fminf(kAlphaMax, e);
+        uint64_t ok = __ballot(alpha >= kAlphaMin) & ~done[k];
+        if (!PLAIN) ok &= __ballot(!(q > g1.y));
+        const float Tk = T[k];
+        const float Tn = __builtin_fmaf(-alpha, Tk, Tk);  // T (1 - alpha)
+        const uint64_t stop = ok & __ballot(Tn < kTMin);
+        const bool blend = __builtin_amdgcn_inverse_ballot_w64(ok & ~stop);
+        done[k] |= stop;
+        const float wgt = blend ? alpha * Tk : 0.0f;
+        C0[k] = __builtin_fmaf(g1.z, wgt, C0[k]);
+        C1[k] = __builtin_fmaf(g1.w, wgt, C1[k]);
+        C2[k] = __builtin_fmaf(cb, wgt, C2[k]);
+        T[k] = blend ? Tn : Tk;
+        if (STATE) last[k] = blend ? pos : last[k];
+        all &= done[k];
+    }
+    return all == ~0ull;
+}
+
 template <int PX, int RW, bool STATE>
 __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                  const uint32_t *__restrict__ ranges, CamK c, float bg0, float bg1,
@@ -39,8 +72,8 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     constexpr int NXR = kTile / RW;     // regions across a tile
     constexpr int WPT = 4 / PX;         // waves per tile
     static_assert(RH <= kTile && (RW == 8 || RW == 16), "wavefront region must tile a 16x16 tile");
-    // s2[i] = {b, bits(list position + 1), -, -}: strided like s0 and s1 so that one address
-    // register serves all three reads
+    // s2[i] = {b, bits(plain << 31 | list position + 1), -, -}: strided like s0 and s1 so
+    // that one address register serves all three reads
     __shared__ float4 s0[kWave], s1[kWave], s2[kWave];
     const int b = blockIdx.x;
     const int L = (b & 7) * per_xcd + (b >> 3);
@@ -81,11 +114,12 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
 #pragma unroll
         for (int k = 0; k < PX; ++k) all_done &= done[k];
         if (all_done == ~0ull) break;
-        bool keep = false;
+        bool keep = false, plain = false;
         float4 f0, f1, f2;
         if (j0 + ln < end) {
             fold_raw(n0, n1, n2, f0, f1, f2);
             keep = !splat_misses(f0, f2, wx0, wx1, wy0, wy1);
+            plain = splat_plain(n0, n1);
         }
         const uint64_t km = __ballot(keep);
         if (keep) {
@@ -94,7 +128,7 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
             s0[pos] = f0;
             s1[pos] = f1;
             s2[pos].x = f2.x;
-            if (STATE) s2[pos].y = __uint_as_float(j0 - start + ln + 1);
+            s2[pos].y = __uint_as_float((plain ? 0x80000000u : 0u) | (j0 - start + ln + 1));
         }
         __syncthreads();
         if (j0 + kWave + ln < end) {
@@ -104,30 +138,23 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
         }
         if (j0 + 2 * kWave + ln < end) gnext = vals[j0 + 2 * kWave + ln];
         const int nb = __popcll(km);
-        for (int i = 0; i < nb; ++i) {
-            const float4 g0 = s0[i], g1 = s1[i];
-            const float cb = s2[i].x;
-            const ColTerms ct = col_terms(g0, g1, sx - g0.x);
-            uint64_t all = ~0ull;
-#pragma unroll
-            for (int k = 0; k < PX; ++k) {
-                const float q = pix_exponent(ct, g1, sy[k] - g0.y);
-                const float alpha = fminf(kAlphaMax, exp2_fast(q));
-                const uint64_t ok = __ballot(!(q > g1.y)) & __ballot(alpha >= kAlphaMin) & ~done[k];
-                const float Tk = T[k];
-                const float Tn = __builtin_fmaf(-alpha, Tk, Tk);  // T (1 - alpha)
-                const uint64_t stop = ok & __ballot(Tn < kTMin);
-                const bool blend = __builtin_amdgcn_inverse_ballot_w64(ok & ~stop);
-                done[k] |= stop;
-                const float wgt = blend ? alpha * Tk : 0.0f;
-                C0[k] = __builtin_fmaf(g1.z, wgt, C0[k]);
-                C1[k] = __builtin_fmaf(g1.w, wgt, C1[k]);
-                C2[k] = __builtin_fmaf(cb, wgt, C2[k]);
-                T[k] = blend ? Tn : Tk;
-                if (STATE) last[k] = blend ? __float_as_uint(s2[i].y) : last[k];
-                all &= done[k];
+        // batches made only of plain splats (nearly all) run the loop without the
+        // positive-exponent test and the clamp
+        if (__ballot(keep && !plain) == 0) {
+            for (int i = 0; i < nb; ++i) {
+                const float2 g2 = *reinterpret_cast<const float2 *>(&s2[i]);
+                const uint32_t pos = __float_as_uint(g2.y) & 0x7fffffffu;
+                if (blend_splat<PX, STATE, true>(s0[i], s1[i], g2.x, pos, sx, sy, T, C0, C1, C2, done, last)) break;
             }
-            if (all == ~0ull) break;
+        } else {
+            for (int i = 0; i < nb; ++i) {
+                const float2 g2 = *reinterpret_cast<const float2 *>(&s2[i]);
+                const uint32_t pos = __float_as_uint(g2.y) & 0x7fffffffu;
+                const bool fin = (__builtin_amdgcn_readfirstlane(__float_as_uint(g2.y)) >> 31)
+                                     ? blend_splat<PX, STATE, true>(s0[i], s1[i], g2.x, pos, sx, sy, T, C0, C1, C2, done, last)
+                                     : blend_splat<PX, STATE, false>(s0[i], s1[i], g2.x, pos, sx, sy, T, C0, C1, C2, done, last);
+                if (fin) break;
+            }
         }
         __syncthreads();
     }

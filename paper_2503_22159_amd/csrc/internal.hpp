@@ -82,10 +82,11 @@ __device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_lo
 // f2.z, f2.w are the half-extents (x, y) of the ellipse where alpha can reach 1/255:
 // amax exp(power) >= 1/255 needs power >= -L, L = ln(255 amax), and -power =
 // 1/2 d^T Q d (Q the conic), so |dx| <= sqrt(2 L Sigma'_xx), |dy| <= sqrt(2 L Sigma'_yy)
-// with Sigma' = Q^-1.  Inflated by 1% + 0.05 px, far beyond FP32 rounding, a splat whose
-// box misses every pixel centre of a wavefront is skipped by that whole wavefront without
-// changing any decision: every pixel would have skipped it.  -1 marks a splat that can
-// never reach 1/255 (amax < 1/255).
+// with Sigma' = Q^-1.  Inflated by 1% + 0.05 px -- far beyond FP32 rounding and the
+// hardware reciprocal / square root used here -- a splat whose box misses every pixel
+// centre of a wavefront is skipped by that whole wavefront without changing any
+// decision: every pixel would have skipped it.  -1 marks a splat that can never reach
+// 1/255 (amax < 1/255).
 __device__ __forceinline__ void fold_raw(const float4 &p, const float4 &q, const float4 &s, float4 &f0, float4 &f1,
                                          float4 &f2) {
     f0 = make_float4(p.x, p.y, (-0.5f * kLog2e) * p.z, (-kLog2e) * p.w);
@@ -96,13 +97,24 @@ __device__ __forceinline__ void fold_raw(const float4 &p, const float4 &q, const
     if (L < -1e-4f) {  // amax clearly below 1/255: no pixel can keep it
         ex = ey = -1.0f;
     } else if (det > 0.0f) {
-        const float k2 = 2.0f * fmaxf(L, 0.0f) / det;
-        ex = sqrtf(k2 * q.x) * 1.01f + 0.05f;
-        ey = sqrtf(k2 * p.z) * 1.01f + 0.05f;
+        const float k2 = 2.0f * fmaxf(L, 0.0f) * __builtin_amdgcn_rcpf(det);
+        ex = __builtin_amdgcn_sqrtf(k2 * q.x) * 1.01f + 0.05f;
+        ey = __builtin_amdgcn_sqrtf(k2 * p.z) * 1.01f + 0.05f;
     } else {  // conic degenerate in FP32: never skip
         ex = ey = 3.0e38f;
     }
     f2 = make_float4(s.x, q.y, ex, ey);
+}
+
+// A splat is "plain" when two of the per-pixel tests cannot fire: its conic is positive
+// definite with margin (so the exponent is never positive, up to rounding at the very
+// centre, where the exact value is 0) and amax < 0.985 (so amax exp(power) stays below
+// the 0.99 clamp).  For plain splats the forward and the backward both drop the
+// "exponent > 0" skip and the clamp; every other splat takes all tests.  Nearly every
+// splat is plain (sigmoid opacities above 0.985 are rare).
+__device__ __forceinline__ bool splat_plain(const float4 &p, const float4 &q) {
+    const float a = p.z, b = p.w, c = q.x;
+    return a > 0.0f && c > 0.0f && a * c - b * b > 1e-5f * (a * c) && q.y < 0.985f;
 }
 
 __device__ __forceinline__ void fold_splat(const float4 *__restrict__ rec, uint32_t gi, float4 &f0, float4 &f1,

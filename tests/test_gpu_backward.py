@@ -102,6 +102,18 @@ def test_parameter_gradients_c3_subset(R, view):
     print("c3 view", view, errs, "masked px", nmask)
 
 
+def test_parameter_gradients_opaque_splats(R):
+    """Every other Gaussian nearly opaque (alpha at the 0.99 clamp, the general per-splat
+    path of forward and backward) next to plain ones."""
+    sc, cam, t = inputs.config1()
+    sc = sc.subset(np.arange(sc.n))
+    sc.opacity[::2] = np.float32(0.9995)
+    sc.t_scale[::2] = np.float32(0.5)
+    ds, st, g, go, gs_o, nmask = run_both(R, sc, cam, t, seed=13)
+    errs = check_params(g, go)
+    print("opaque grad rel err", errs, "masked px", nmask)
+
+
 def test_backward_is_deterministic(R):
     import torch
 

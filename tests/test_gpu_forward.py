@@ -97,6 +97,17 @@ def test_dense_tiles_every_sort_path(R, n):
     check_frame(R, sc, cam, np.float32(0.5), bg=(0.1, 0.2, 0.3))
 
 
+def test_opaque_splats_take_the_clamp_path(R):
+    """Every other Gaussian nearly opaque: their alpha reaches the 0.99 clamp, so they take
+    the blend's general per-splat path (positive-exponent skip and clamp evaluated) and
+    share batches with plain splats."""
+    sc, cam, t = inputs.config1()
+    sc = sc.subset(np.arange(sc.n))
+    sc.opacity[::2] = np.float32(0.9995)
+    sc.t_scale[::2] = np.float32(0.5)
+    check_frame(R, sc, cam, t, bg=(0.2, 0.2, 0.2))
+
+
 def test_empty_and_all_culled(R):
     sc, cam, t = inputs.config1()
     empty = sc.subset(np.arange(0))
