@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-times", action="store_true", help="skip the multi-timestamp batch measurement")
     ap.add_argument("--cpu-frames", type=int, default=100)
     ap.add_argument("--bwd-frames", type=int, default=20)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -175,6 +176,43 @@ def fwd_bwd(args, ds, cams, render, inputs):
             "frames": len(views), "camera_cache": False}
 
 
+def times_batch(args, ds, cams, render):
+    """Fixed-viewpoint multi-timestamp rendering (d4dgs_render_times) at camera 10: wall
+    time per call of T frames, and the marginal cost and device memory of one more frame
+    (the paper's parallel-frame measurement)."""
+    import numpy as np
+    import torch
+
+    W, H = cams[0].width, cams[0].height
+    cam = cams[10]
+    Ts, ms = [], []
+    frame_bytes = None
+    for T in (1, 2, 4, 8, 16, 32):
+        tr = render.TimesRenderer(ds, W, H, T, capacity=4 * ds.n, cache=True)
+        times = [np.float32((k + 0.5) / T) for k in range(T)]
+        for _ in range(2):
+            tr.render(cam, times)
+        torch.cuda.synchronize()
+        reps = max(4, 128 // T)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            tr.render(cam, times)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert not tr.overflowed()
+        Ts.append(T)
+        ms.append(1000.0 * el / reps)
+        if frame_bytes is None:
+            f = tr.frames[0]
+            frame_bytes = sum(x.numel() * x.element_size() for x in
+                              (f.rec, f.count, f.offset, f.partial, f.keys, f.values, f.ranges, f.ws, tr.imgs[0]))
+        del tr
+    slope = float(np.polyfit(np.array(Ts, float), np.array(ms), 1)[0])
+    return {"camera": 10, "T": Ts, "ms_per_call": [round(x, 4) for x in ms],
+            "frames_per_s": [round(T / (m * 1e-3), 1) for T, m in zip(Ts, ms)],
+            "ms_per_extra_frame": round(slope, 4), "device_bytes_per_frame": int(frame_bytes)}
+
+
 def cpu_baseline(args, scene, cams, times):
     """The oracle (plain C + OpenMP, FP32 decisions / FP64 blend) on a bounded sample of
     the timed frames; also returns the oracle's count of blend evaluations."""
@@ -240,6 +278,8 @@ def main():
     }
     if not args.no_bwd:
         out["fwd_bwd"] = fwd_bwd(args, ds, cams, render, inputs)
+    if not args.no_times:
+        out["times_batch"] = times_batch(args, ds, cams, render)
     if not args.no_serve:
         try:
             from paper_2503_22159_amd import serve_bench

@@ -210,6 +210,26 @@ d4dgs_status d4dgs_render_bwd(const d4dgs_scene *scene, const d4dgs_camera *cam,
                               const float *final_T, const uint32_t *n_contrib, const float *dL_dimg,
                               float *inst_grads, d4dgs_grads *grads, d4dgs_stream stream);
 
+/* Fixed-viewpoint multi-timestamp rendering: the parallel rendering of several frames of
+ * one camera that the paper reports (Sec. 4, rendering speed), through Alg. 1 with the
+ * camera branch taken once.  Frames i = 0..T-1 at times t[i]:
+ *   - the camera stage runs once (not at all on a cache hit; cache may be NULL), and the
+ *     time stages of up to 16 frames run in one launch, so the splat records are
+ *     bit-identical to d4dgs_project at each t[i];
+ *   - each frame is then binned, sorted and blended as by d4dgs_bin_sort +
+ *     d4dgs_render_fwd (without replay state), with the frames spread over the library's
+ *     own streams of the current device, forked from and joined back onto `stream`.
+ * t (host) [T]; splats, bins (host arrays of T structs) and workspace, img (host arrays
+ * of T device pointers) describe each frame's buffers as for the single-frame calls;
+ * every workspace holds workspace_bytes >= d4dgs_workspace_size for its frame.  If a
+ * frame's instances exceed its bins capacity, *d_status (device int32, may be NULL) is
+ * set to D4DGS_ERR_CAPACITY and that frame renders only the background.  Calls on one
+ * device are serialised against each other while they enqueue. */
+d4dgs_status d4dgs_render_times(const d4dgs_scene *scene, const d4dgs_camera *cam, int32_t T, const float *t,
+                                d4dgs_cam_cache *cache, d4dgs_splats *splats, d4dgs_bins *bins,
+                                void *const *workspace, size_t workspace_bytes, const float bg[3],
+                                float *const *img, int32_t *d_status, d4dgs_stream stream);
+
 /* ------------------------------------------------------------------ serving ------
  * A server keeps one scene resident and renders requests (camera, t, resolution) as
  * they arrive.  Requests are admitted while fewer than max_inflight are on the GPU and

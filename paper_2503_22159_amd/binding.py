@@ -83,7 +83,7 @@ class D4Error(RuntimeError):
 EXPORTS = ("d4dgs_abi_version", "d4dgs_last_error", "d4dgs_workspace_size", "d4dgs_project", "d4dgs_bin_sort",
            "d4dgs_bin_sort_sync", "d4dgs_render_fwd", "d4dgs_render_bwd", "d4dgs_serve_create",
            "d4dgs_serve_submit", "d4dgs_serve_poll", "d4dgs_serve_wait", "d4dgs_serve_stats_get",
-           "d4dgs_serve_destroy")
+           "d4dgs_serve_destroy", "d4dgs_render_times")
 
 
 def _load():
@@ -111,6 +111,10 @@ def _load():
         "d4dgs_serve_wait": (C.c_int, [P, C.c_uint64, C.c_int64, C.POINTER(ReqStats)]),
         "d4dgs_serve_stats_get": (C.c_int, [P, C.POINTER(ServeStats)]),
         "d4dgs_serve_destroy": (C.c_int, [P]),
+        "d4dgs_render_times": (C.c_int, [C.POINTER(Scene), C.POINTER(Camera), C.c_int32, C.POINTER(C.c_float),
+                                         C.POINTER(CamCache), C.POINTER(Splats), C.POINTER(Bins),
+                                         C.POINTER(C.c_void_p), C.c_size_t, C.POINTER(C.c_float * 3),
+                                         C.POINTER(C.c_void_p), P, P]),
     }
     for name, (res, args) in sig.items():
         try:

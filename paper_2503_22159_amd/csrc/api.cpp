@@ -1,8 +1,13 @@
 // C ABI of libd4dgs: argument checks, the camera-stage cache, workspace carving and
-// launches.  Every entry point enqueues on the caller's stream and returns.
+// launches.  Every entry point enqueues on the caller's stream and returns
+// (d4dgs_render_times forks onto its own streams and joins back onto the caller's).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -263,6 +268,119 @@ d4dgs_status d4dgs_render_bwd(const d4dgs_scene *scene, const d4dgs_camera *cam,
         e = launch_project_bwd(sk, ck, t, (const float4 *)splats->rec, splats->count, splats->offset,
                                (const float4 *)inst_grads, bins->capacity, *grads, (hipStream_t)stream);
     return hip_status(e, "d4dgs_render_bwd");
+}
+
+// Streams and events of d4dgs_render_times, one set per device, created on first use
+// and kept until the process ends.
+struct TimesPool {
+    static constexpr int kStreams = 3;
+    std::mutex mu;
+    bool ready = false;
+    hipStream_t s[kStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kStreams] = {};
+};
+
+static TimesPool *times_pool(int dev) {
+    static std::mutex mu;
+    static std::vector<std::unique_ptr<TimesPool>> pools;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)pools.size() <= dev) pools.resize(dev + 1);
+    if (!pools[dev]) pools[dev].reset(new TimesPool());
+    return pools[dev].get();
+}
+
+d4dgs_status d4dgs_render_times(const d4dgs_scene *scene, const d4dgs_camera *cam, int32_t T, const float *t,
+                                d4dgs_cam_cache *cache, d4dgs_splats *splats, d4dgs_bins *bins,
+                                void *const *workspace, size_t workspace_bytes, const float bg[3],
+                                float *const *img, int32_t *d_status, d4dgs_stream stream) {
+    D4_TRY(check_scene(scene));
+    D4_TRY(check_camera(cam));
+    if (T < 1 || T > (1 << 20)) return fail(D4DGS_ERR_INVALID_ARG, "render_times: T out of range");
+    if (!t || !splats || !bins || !workspace || !img || !bg)
+        return fail(D4DGS_ERR_INVALID_ARG, "render_times: NULL argument");
+    const CamK ck = make_camk(*cam);
+    const int tiles = ck.TX * ck.TY;
+    for (int i = 0; i < T; ++i) {
+        if (!std::isfinite(t[i])) return fail(D4DGS_ERR_INVALID_ARG, "render_times: t not finite");
+        D4_TRY(check_splats(&splats[i], scene->n));
+        D4_TRY(check_bins(&bins[i]));
+        if (!workspace[i] || !img[i]) return fail(D4DGS_ERR_INVALID_ARG, "render_times: NULL frame buffer");
+        if (workspace_bytes < sort_workspace_bytes(scene->n, bins[i].capacity, tiles))
+            return fail(D4DGS_ERR_OUT_OF_MEMORY, "render_times: workspace smaller than d4dgs_workspace_size");
+    }
+    int mode = 0;
+    float *crec = nullptr;
+    int ccap = 0;
+    if (cache) {
+        if (!cache->rec || cache->capacity < scene->n)
+            return fail(D4DGS_ERR_OUT_OF_MEMORY, "camera cache capacity smaller than n");
+        crec = cache->rec;
+        ccap = cache->capacity;
+        const bool hit = cache->valid && cache->scene_key == (const void *)scene->mean && cache->scene_n == scene->n &&
+                         cache->scene_sh_degree == scene->sh_degree &&
+                         std::memcmp(&cache->cam, cam, sizeof(d4dgs_camera)) == 0;
+        mode = hit ? 2 : 1;
+        if (hit) cache->hits++; else cache->misses++;
+    }
+    int dev = 0;
+    D4_TRY(hip_status(hipGetDevice(&dev), "render_times: hipGetDevice"));
+    TimesPool *pool = times_pool(dev);
+    std::lock_guard<std::mutex> lk(pool->mu);
+    if (!pool->ready) {
+        for (int k = 0; k < TimesPool::kStreams; ++k) {
+            D4_TRY(hip_status(hipStreamCreateWithFlags(&pool->s[k], hipStreamNonBlocking), "render_times: stream"));
+            D4_TRY(hip_status(hipEventCreateWithFlags(&pool->join[k], hipEventDisableTiming), "render_times: event"));
+        }
+        D4_TRY(hip_status(hipEventCreateWithFlags(&pool->fork, hipEventDisableTiming), "render_times: event"));
+        pool->ready = true;
+    }
+    const hipStream_t st = (hipStream_t)stream;
+    const SceneK sk = make_scenek(*scene);
+    hipError_t e = hipSuccess;
+    // time stages, kMaxTimes frames per launch; the first launch runs the camera stage
+    for (int c0 = 0; c0 < T && e == hipSuccess; c0 += kMaxTimes) {
+        TimesArgs a;
+        a.nt = std::min(kMaxTimes, T - c0);
+        for (int f = 0; f < a.nt; ++f) {
+            const d4dgs_splats &sp = splats[c0 + f];
+            a.f[f] = FrameK{t[c0 + f], (float4 *)sp.rec, sp.count, sp.partial};
+        }
+        const int m = c0 == 0 ? mode : (cache ? 2 : 0);
+        e = launch_project_times(sk, ck, m, crec, ccap, a, st);
+    }
+    if (e != hipSuccess) {
+        if (cache) cache->valid = 0;
+        return hip_status(e, "render_times: projection");
+    }
+    if (cache && mode == 1) {
+        cache->cam = *cam;
+        cache->scene_key = (const void *)scene->mean;
+        cache->scene_n = scene->n;
+        cache->scene_sh_degree = scene->sh_degree;
+        cache->valid = 1;
+    }
+    // fork: per-frame binning, sort and blend over the pool's streams
+    const int S = std::min(TimesPool::kStreams, T);
+    e = hipEventRecord(pool->fork, st);
+    for (int k = 0; k < S && e == hipSuccess; ++k) e = hipStreamWaitEvent(pool->s[k], pool->fork, 0);
+    for (int i = 0; i < T && e == hipSuccess; ++i) {
+        const hipStream_t fs = pool->s[i % S];
+        const SortWs ws = carve_workspace(workspace[i], scene->n, bins[i].capacity, tiles);
+        e = launch_bin_sort((const float4 *)splats[i].rec, splats[i].count, splats[i].offset, splats[i].partial,
+                            scene->n, ck, ws, bins[i].keys, bins[i].values, bins[i].ranges, bins[i].num_instances,
+                            bins[i].capacity, d_status, fs);
+        if (e == hipSuccess)
+            e = launch_blend((const float4 *)splats[i].rec, bins[i].values, bins[i].ranges, ck, bg, img[i], nullptr,
+                             nullptr, fs);
+    }
+    // join (also after a failed launch, so that the caller's stream never runs ahead)
+    for (int k = 0; k < S; ++k) {
+        const hipError_t e2 = hipEventRecord(pool->join[k], pool->s[k]);
+        const hipError_t e3 = e2 == hipSuccess ? hipStreamWaitEvent(st, pool->join[k], 0) : e2;
+        if (e == hipSuccess) e = e3;
+    }
+    return hip_status(e, "render_times");
 }
 
 }  // extern "C"

@@ -170,6 +170,22 @@ struct BatchArgs {
 };
 hipError_t launch_project_batch(const SceneK &s, const BatchArgs &args, hipStream_t st);
 
+// One frame of a fixed-viewpoint multi-timestamp projection (kernel argument, by value).
+struct FrameK {
+    float t;
+    float4 *rec;
+    uint32_t *count;
+    uint32_t *partial;
+};
+constexpr int kMaxTimes = 16;  // frames per multi-timestamp projection launch
+struct TimesArgs {
+    int nt;
+    FrameK f[kMaxTimes];
+};
+// mode as launch_project (0: no cache, 1: fill the cache, 2: from the cache)
+hipError_t launch_project_times(const SceneK &s, const CamK &c, int mode, float *cam_rec, int cam_cap,
+                                const TimesArgs &args, hipStream_t st);
+
 struct SortWs {
     uint64_t *bucket;    // [capacity] per-tile buckets of (depth bits << 32 | gaussian)
     uint64_t *alt;       // [capacity] scratch of the large-bucket radix sort

@@ -322,6 +322,84 @@ __global__ __launch_bounds__(kBlock) void k_project_batch(SceneK s, BatchArgs ar
     }
 }
 
+// Fixed-viewpoint multi-timestamp projection (Alg. 1 with one camera and many t): each
+// thread obtains its Gaussian's camera record once -- from the cache (MODE 2), or by the
+// camera stage (MODE 0; MODE 1 also stores it in the cache) -- and runs the time stage for
+// every frame of the launch, writing each frame's record, count and block sums.  The
+// arithmetic is that of k_project, so every frame is bit-identical to a single-frame
+// projection at its t.
+template <int MODE, int DEG>
+__global__ __launch_bounds__(kBlock) void k_project_times(SceneK s, CamK c, float *__restrict__ cam_rec, int cap,
+                                                         TimesArgs args) {
+    const int gi = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = gi < s.n;
+    CamRec cr;
+    bool ok = false;
+    float op = 0.f, mut = 0.f, st = 1.f;
+    if (valid) {
+        op = s.opacity[gi];
+        mut = s.t_mean[gi];
+        st = s.t_scale[gi];
+        if (MODE == 2) {
+            ok = true;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) cr.p[i] = cam_rec[(size_t)i * cap + gi];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) cr.u[i] = cam_rec[(size_t)(3 + i) * cap + gi];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) cr.cv[i] = cam_rec[(size_t)(6 + i) * cap + gi];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                cr.m0[i] = cam_rec[(size_t)(12 + i) * cap + gi];
+                cr.md[i] = cam_rec[(size_t)(14 + i) * cap + gi];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) cr.rgb[i] = cam_rec[(size_t)(16 + i) * cap + gi];
+            // a Gaussian the camera stage culled is stored with p = (0, 0, -1): the time
+            // stage's near test culls it
+        } else {
+            GParams<DEG> P;
+            load_params<DEG>(s, gi, P);
+            ok = P.ok;
+            if (ok) {
+                camera_stage<DEG>(P, c, cr);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) cr.p[i] = 0.0f;
+                cr.p[2] = -1.0f;
+            }
+            if (MODE == 1) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) cam_rec[(size_t)i * cap + gi] = cr.p[i];
+                if (ok) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) cam_rec[(size_t)(3 + i) * cap + gi] = cr.u[i];
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) cam_rec[(size_t)(6 + i) * cap + gi] = cr.cv[i];
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        cam_rec[(size_t)(12 + i) * cap + gi] = cr.m0[i];
+                        cam_rec[(size_t)(14 + i) * cap + gi] = cr.md[i];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) cam_rec[(size_t)(16 + i) * cap + gi] = cr.rgb[i];
+                }
+            }
+        }
+    }
+    for (int f = 0; f < args.nt; ++f) {
+        const FrameK &q = args.f[f];
+        uint32_t cnt = 0;
+        if (valid && ok) {
+            float4 r0, r1, r2;
+            cnt = time_stage(cr, op, mut, st, q.t, c, r0, r1, r2);
+            if (cnt) store_rec(q.rec, gi, r0, r1, r2);
+        }
+        if (valid) q.count[gi] = cnt;
+        block_count_sum(cnt, q.partial);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, float *cam_rec, int cam_cap,
@@ -358,6 +436,34 @@ hipError_t launch_project_batch(const SceneK &s, const BatchArgs &args, hipStrea
         case 2: hipLaunchKernelGGL(k_project_batch<2>, dim3(grid), dim3(kBlock), 0, st, s, args); break;
         default: hipLaunchKernelGGL(k_project_batch<3>, dim3(grid), dim3(kBlock), 0, st, s, args); break;
     }
+    return hipGetLastError();
+}
+
+}  // namespace d4
+
+namespace d4 {
+
+hipError_t launch_project_times(const SceneK &s, const CamK &c, int mode, float *cam_rec, int cam_cap,
+                                const TimesArgs &args, hipStream_t st) {
+    if (s.n == 0 || args.nt == 0) return hipSuccess;
+    const int grid = (s.n + kBlock - 1) / kBlock;
+#define D4_LAUNCH(M, D) \
+    hipLaunchKernelGGL((k_project_times<M, D>), dim3(grid), dim3(kBlock), 0, st, s, c, cam_rec, cam_cap, args)
+    if (mode == 2) {
+        D4_LAUNCH(2, 0);
+    } else {
+        switch (s.deg * 2 + mode) {
+            case 0: D4_LAUNCH(0, 0); break;
+            case 1: D4_LAUNCH(1, 0); break;
+            case 2: D4_LAUNCH(0, 1); break;
+            case 3: D4_LAUNCH(1, 1); break;
+            case 4: D4_LAUNCH(0, 2); break;
+            case 5: D4_LAUNCH(1, 2); break;
+            case 6: D4_LAUNCH(0, 3); break;
+            default: D4_LAUNCH(1, 3); break;
+        }
+    }
+#undef D4_LAUNCH
     return hipGetLastError();
 }
 

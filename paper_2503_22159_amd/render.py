@@ -296,3 +296,45 @@ class Renderer:
     def overflowed(self):
         """True if any frame since the last reset exceeded the instance capacity."""
         return int(self.st.status.item()) != 0
+
+
+class TimesRenderer:
+    """Fixed buffers for T frames of one camera at T times, rendered by one
+    d4dgs_render_times call (camera stage once, batched time stages, per-frame binning
+    and blending on the library's own streams)."""
+
+    def __init__(self, scene: DeviceScene, width, height, T, capacity=None, cache=True):
+        self.scene = scene
+        self.width, self.height, self.T = int(width), int(height), int(T)
+        dev = scene.t["mean"].device
+        cap = capacity or default_capacity(scene.n, width, height)
+        self.frames = [FrameState(scene.n, self.width, self.height, cap, dev) for _ in range(self.T)]
+        self.imgs = [torch.empty((3, self.height, self.width), dtype=torch.float32, device=dev) for _ in range(self.T)]
+        self.cache = CamCache(scene.n, dev) if cache else None
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self._scene_s = scene.struct()
+        self._sp = (B.Splats * self.T)(*[f.splats() for f in self.frames])
+        self._bn = (B.Bins * self.T)(*[f.bins() for f in self.frames])
+        self._ws = (C.c_void_p * self.T)(*[f.ws.data_ptr() for f in self.frames])
+        self._ws_bytes = min(f.ws.numel() for f in self.frames)
+        self._img = (C.c_void_p * self.T)(*[im.data_ptr() for im in self.imgs])
+        self._t = (C.c_float * self.T)()
+        self._cams = {}
+
+    def render(self, cam, times, bg=(0.0, 0.0, 0.0), stream=None):
+        """Renders self.T frames at `times` (length T); returns the T image tensors."""
+        assert cam.width == self.width and cam.height == self.height and len(times) == self.T
+        hit = self._cams.get(id(cam))
+        if hit is None or hit[0] is not cam:
+            hit = (cam, B.camera_struct(cam))
+            self._cams[id(cam)] = hit
+        for i, t in enumerate(times):
+            self._t[i] = float(t)
+        B.check(B.lib.d4dgs_render_times(C.byref(self._scene_s), C.byref(hit[1]), self.T, self._t,
+                                         C.byref(self.cache.c) if self.cache is not None else None, self._sp,
+                                         self._bn, self._ws, self._ws_bytes, C.byref(_bg(bg)), self._img,
+                                         _ptr(self.status), stream or _stream()))
+        return self.imgs
+
+    def overflowed(self):
+        return int(self.status.item()) != 0
