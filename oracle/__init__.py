@@ -13,6 +13,9 @@ Functions follow the paper's pipeline (Alg. 1 and Sec. 3.2):
     project_bwd(...)               projection adjoint by the complex-step method
     render(scene, cam, t, bg)      project(f32) -> bin -> blend
     render_grad(...)               gradients of sum(dL_dimg * image) w.r.t. parameters
+    blend(..., flow=True)          also the optical flow of Sec. 3.3, F = sum md a T
+    flow_loss(img, flow, lam, eps) the flow-gradient guided consistency loss (Eq. 16-17)
+                                   and its gradient with respect to the flow
 
 Precision: everything that decides an integer (culls, rectangles, depth keys) runs
 in FP32 in the fixed operation order of the FP contract; blending and gradients run
@@ -83,8 +86,14 @@ def lib():
         L.oc_blend_bruteforce.restype = None
         L.oc_blend_bwd.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 13
         L.oc_blend_bwd.restype = None
+        L.oc_blend_flow.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 13
+        L.oc_blend_flow.restype = C.c_int64
+        L.oc_blend_bwd_flow.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 16
+        L.oc_blend_bwd_flow.restype = None
         L.oc_project_bwd.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 6
         L.oc_project_bwd.restype = None
+        L.oc_project_bwd_flow.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 7
+        L.oc_project_bwd_flow.restype = None
         L.oc_sh_basis.argtypes = [C.c_int, C.c_int, P, P]
         L.oc_sh_basis.restype = None
         L.oc_set_threads.argtypes = [C.c_int]
@@ -180,7 +189,10 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def blend(proj, bins, cam, bg=(0.0, 0.0, 0.0)):
+def blend(proj, bins, cam, bg=(0.0, 0.0, 0.0), flow=False):
+    """Eq. 4 per pixel.  flow=True also blends the screen velocity md of each splat with
+    the same weights (the rendered optical flow of Sec. 3.3, background 0) into
+    res["flow"] [2][H][W]."""
     n, W, H = proj["n"], cam.width, cam.height
     img = np.zeros((3, H, W))
     T = np.zeros((H, W))
@@ -189,6 +201,13 @@ def blend(proj, bins, cam, bg=(0.0, 0.0, 0.0)):
     dh = np.zeros((H, W), np.uint64)
     vals = bins["values"] if bins["I"] > 0 else np.zeros(1, np.uint32)
     bgv = _f64(bg)
+    if flow:
+        fo = np.zeros((2, H, W))
+        ne = lib().oc_blend_flow(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])), _p(_f64(proj["amax"])),
+                                 _p(_f64(proj["rgb"])), _p(_f64(proj["md"])), _p(np.ascontiguousarray(vals)),
+                                 _p(np.ascontiguousarray(bins["ranges"], np.uint32)), _p(bgv), _p(img), _p(fo),
+                                 _p(T), _p(nc), _p(fl))
+        return {"img": img, "flow": fo, "final_T": T, "n_contrib": nc, "flags": fl, "n_eval": int(ne)}
     ne = lib().oc_blend(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])), _p(_f64(proj["amax"])),
                         _p(_f64(proj["rgb"])), _p(np.ascontiguousarray(vals)),
                         _p(np.ascontiguousarray(bins["ranges"], np.uint32)), _p(bgv), _p(img), _p(T),
@@ -211,15 +230,25 @@ def blend_bruteforce(proj, cam, bg=(0.0, 0.0, 0.0)):
     return {"img": img, "final_T": T, "n_contrib": nc, "flags": fl}
 
 
-def blend_bwd(proj, bins, cam, dL_dimg, bg=(0.0, 0.0, 0.0)):
+def blend_bwd(proj, bins, cam, dL_dimg, bg=(0.0, 0.0, 0.0), dL_dflow=None):
+    """Adjoint of blend: splat-level gradients of sum(dL_dimg * img) (+ sum(dL_dflow *
+    flow) when dL_dflow is given, then also g["md"])."""
     n, W, H = proj["n"], cam.width, cam.height
     g = {"m": np.zeros((2, n)), "conic": np.zeros((3, n)), "amax": np.zeros(n), "rgb": np.zeros((3, n))}
     err = np.zeros(1)
     vals = bins["values"] if bins["I"] > 0 else np.zeros(1, np.uint32)
-    lib().oc_blend_bwd(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])), _p(_f64(proj["amax"])),
-                       _p(_f64(proj["rgb"])), _p(np.ascontiguousarray(vals)),
-                       _p(np.ascontiguousarray(bins["ranges"], np.uint32)), _p(_f64(bg)),
-                       _p(_f64(dL_dimg)), _p(g["m"]), _p(g["conic"]), _p(g["amax"]), _p(g["rgb"]), _p(err))
+    if dL_dflow is not None:
+        g["md"] = np.zeros((2, n))
+        lib().oc_blend_bwd_flow(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])), _p(_f64(proj["amax"])),
+                                _p(_f64(proj["rgb"])), _p(_f64(proj["md"])), _p(np.ascontiguousarray(vals)),
+                                _p(np.ascontiguousarray(bins["ranges"], np.uint32)), _p(_f64(bg)),
+                                _p(_f64(dL_dimg)), _p(_f64(dL_dflow)), _p(g["m"]), _p(g["conic"]),
+                                _p(g["amax"]), _p(g["rgb"]), _p(g["md"]), _p(err))
+    else:
+        lib().oc_blend_bwd(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])), _p(_f64(proj["amax"])),
+                           _p(_f64(proj["rgb"])), _p(np.ascontiguousarray(vals)),
+                           _p(np.ascontiguousarray(bins["ranges"], np.uint32)), _p(_f64(bg)),
+                           _p(_f64(dL_dimg)), _p(g["m"]), _p(g["conic"]), _p(g["amax"]), _p(g["rgb"]), _p(err))
     g["replay_rel_err"] = float(err[0])
     return g
 
@@ -234,9 +263,10 @@ def project_bwd(scene, cam, t, active, gsplat, arrays=None):
     s, keep = _scene_struct(arr, n, deg)
     c = _cam_struct(cam)
     out = np.zeros((P, n))
-    lib().oc_project_bwd(C.byref(s), C.byref(c), float(t), _p(np.ascontiguousarray(active, np.int32)),
-                         _p(_f64(gsplat["m"])), _p(_f64(gsplat["conic"])), _p(_f64(gsplat["amax"])),
-                         _p(_f64(gsplat["rgb"])), _p(out))
+    gmd = gsplat.get("md")
+    lib().oc_project_bwd_flow(C.byref(s), C.byref(c), float(t), _p(np.ascontiguousarray(active, np.int32)),
+                              _p(_f64(gsplat["m"])), _p(_f64(gsplat["conic"])), _p(_f64(gsplat["amax"])),
+                              _p(_f64(gsplat["rgb"])), _p(_f64(gmd)) if gmd is not None else None, _p(out))
     del keep
     return unpack_params(out, K)
 
@@ -250,25 +280,96 @@ def unpack_params(flat, K):
     return res
 
 
-def render(scene, cam, t, bg=(0.0, 0.0, 0.0), prec="f32", arrays=None):
+def render(scene, cam, t, bg=(0.0, 0.0, 0.0), prec="f32", arrays=None, flow=False):
     """project -> bin -> blend.  Returns (projection, bins, blend result)."""
     proj = project(scene, cam, t, prec, arrays)
     bins = bin(proj, cam)
-    res = blend(proj, bins, cam, bg)
+    res = blend(proj, bins, cam, bg, flow=flow)
     return proj, bins, res
 
 
-def render_grad(scene, cam, t, dL_dimg, bg=(0.0, 0.0, 0.0), prec="f32", arrays=None, mask=None):
-    """Gradient of sum(dL_dimg * image) with respect to every parameter.  `mask`
-    (H, W) zeroes the upstream gradient at excluded pixels."""
-    proj, bins, res = render(scene, cam, t, bg, prec, arrays)
+def render_grad(scene, cam, t, dL_dimg, bg=(0.0, 0.0, 0.0), prec="f32", arrays=None, mask=None, dL_dflow=None):
+    """Gradient of sum(dL_dimg * image) (+ sum(dL_dflow * flow)) with respect to every
+    parameter.  `mask` (H, W) zeroes the upstream gradients at excluded pixels."""
+    proj, bins, res = render(scene, cam, t, bg, prec, arrays, flow=dL_dflow is not None)
     gin = np.array(dL_dimg, dtype=np.float64)
+    gfl = None if dL_dflow is None else np.array(dL_dflow, dtype=np.float64)
     if mask is not None:
         gin = gin * (~mask)[None]
-    gs = blend_bwd(proj, bins, cam, gin, bg)
+        if gfl is not None:
+            gfl = gfl * (~mask)[None]
+    gs = blend_bwd(proj, bins, cam, gin, bg, dL_dflow=gfl)
     active = (proj["count"] > 0).astype(np.int32)
     gp = project_bwd(scene, cam, t, active, gs, arrays)
     return gp, gs, (proj, bins, res)
+
+
+# ---------------- flow-gradient guided consistency loss (Sec. 3.3, Eq. 16-17) -------------
+# Readings (the paper leaves these open):
+#  * gradients by the 3x3 Sobel operator, Kx = [[-1,0,1],[-2,0,2],[-1,0,1]] (x along a
+#    row), Ky its transpose, as a correlation over the pixels whose 3x3 neighbourhood
+#    lies inside the image ("interior" pixels); N counts them;
+#  * |grad I| over the RGB image = sqrt(sum over channels of Gx^2 + Gy^2);
+#  * "normalized" = divided by its largest value over the interior, floored at
+#    NORM_FLOOR (so that rounding noise of a flat image or flow is not blown up to 1);
+#  * L = lam / N * sum_interior nM (1 - nI), M = sqrt(u^2 + v^2 + eps);
+#  * the loss shapes the motion: its gradient is taken with respect to the flow, with
+#    the image-edge weight (1 - nI) and both normalisers held constant.
+SOBEL_X = np.array([[-1.0, 0.0, 1.0], [-2.0, 0.0, 2.0], [-1.0, 0.0, 1.0]])
+NORM_FLOOR = 1e-6
+SOBEL_Y = SOBEL_X.T.copy()
+
+
+def sobel(f):
+    """(Gx, Gy) of a 2D array over its interior pixels, shape (H-2, W-2): a plain sum over
+    the nine taps."""
+    f = np.asarray(f, np.float64)
+    H, W = f.shape
+    gx = np.zeros((H - 2, W - 2))
+    gy = np.zeros((H - 2, W - 2))
+    for j in range(3):
+        for i in range(3):
+            win = f[j:j + H - 2, i:i + W - 2]
+            gx += SOBEL_X[j, i] * win
+            gy += SOBEL_Y[j, i] * win
+    return gx, gy
+
+
+def flow_loss(img, flow, lam, eps, norms=None):
+    """L_fg of Eq. 17 and dL/dflow ([2][H][W]).  `norms` = the two normalisers
+    (max(max |grad M|, floor), max(max |grad I|, floor)) to use instead (finite-difference
+    checks hold them fixed).  Returns (loss, dL_dflow, info)."""
+    img = np.asarray(img, np.float64)
+    flow = np.asarray(flow, np.float64)
+    _, H, W = img.shape
+    if H < 3 or W < 3:
+        return 0.0, np.zeros_like(flow), {"N": 0, "max_gM": 0.0, "max_gI": 0.0}
+    u, v = flow
+    M = np.sqrt(u * u + v * v + eps)
+    gxM, gyM = sobel(M)
+    gM = np.sqrt(gxM * gxM + gyM * gyM)
+    gI2 = np.zeros((H - 2, W - 2))
+    for c in range(3):
+        gx, gy = sobel(img[c])
+        gI2 += gx * gx + gy * gy
+    gI = np.sqrt(gI2)
+    mM, mI = (max(gM.max(), NORM_FLOOR), max(gI.max(), NORM_FLOOR)) if norms is None else norms
+    nM = gM / mM
+    nI = gI / mI
+    N = (H - 2) * (W - 2)
+    loss = lam / N * float(np.sum(nM * (1.0 - nI)))
+    # backward (edge weight and normalisers constant)
+    wgt = lam / N * (1.0 - nI) / mM
+    safe = np.where(gM > 0, gM, 1.0)
+    cx = np.where(gM > 0, wgt * gxM / safe, 0.0)
+    cy = np.where(gM > 0, wgt * gyM / safe, 0.0)
+    dM = np.zeros((H, W))
+    for j in range(3):
+        for i in range(3):
+            dM[j:j + H - 2, i:i + W - 2] += SOBEL_X[j, i] * cx + SOBEL_Y[j, i] * cy
+    Ms = np.where(M > 0, M, 1.0)  # M = 0 only with eps = 0 at zero flow: gradient 0 there
+    dflow = np.stack([np.where(M > 0, dM * u / Ms, 0.0), np.where(M > 0, dM * v / Ms, 0.0)])
+    return loss, dflow, {"N": N, "max_gM": float(mM), "max_gI": float(mI)}
 
 
 def sh_basis(deg, dirs):

@@ -291,9 +291,10 @@ int64_t oc_bin(int n, int W, int H, const int32_t *rect, const int32_t *count, c
 }
 
 /* ---------------- blending (O1: tiled) ---------------- */
-int64_t oc_blend(int n, int W, int H, const double *m, const double *conic, const double *amax,
-                 const double *rgb, const uint32_t *values, const uint32_t *ranges, const double *bg,
-                 double *img, double *final_T, int32_t *n_contrib, int32_t *flags, uint64_t *dhash)
+static int64_t blend_tiled(int n, int W, int H, const double *m, const double *conic, const double *amax,
+                           const double *rgb, const double *md, const uint32_t *values, const uint32_t *ranges,
+                           const double *bg, double *img, double *flow, double *final_T, int32_t *n_contrib,
+                           int32_t *flags, uint64_t *dhash)
 {
     int TX = (W + 15) / 16, TY = (H + 15) / 16;
     int64_t total = 0;
@@ -303,20 +304,40 @@ int64_t oc_blend(int n, int W, int H, const double *m, const double *conic, cons
         uint32_t s0 = ranges[2 * tile], s1 = ranges[2 * tile + 1];
         for (int py = ty * 16; py < ty * 16 + 16 && py < H; ++py)
             for (int px = tx * 16; px < tx * 16 + 16 && px < W; ++px) {
-                double out[3], T;
+                double out[3], fo[2], T;
                 int nc, fl;
                 int64_t ne = 0;
                 size_t pi = (size_t)py * W + px;
-                blend_pixel_f64(n, m, conic, amax, rgb, values + s0, (int)(s1 - s0), px + 0.5, py + 0.5, bg,
-                                out, &T, &nc, &fl, &ne, dhash ? dhash + pi : NULL);
+                blend_pixel_f64(n, m, conic, amax, rgb, md, values + s0, (int)(s1 - s0), px + 0.5, py + 0.5, bg,
+                                out, fo, &T, &nc, &fl, &ne, dhash ? dhash + pi : NULL);
                 total += ne;
                 for (int c = 0; c < 3; ++c) img[(size_t)c * W * H + pi] = out[c];
+                if (md)
+                    for (int c = 0; c < 2; ++c) flow[(size_t)c * W * H + pi] = fo[c];
                 if (final_T) final_T[pi] = T;
                 if (n_contrib) n_contrib[pi] = nc;
                 if (flags) flags[pi] = fl;
             }
     }
     return total;
+}
+
+int64_t oc_blend(int n, int W, int H, const double *m, const double *conic, const double *amax,
+                 const double *rgb, const uint32_t *values, const uint32_t *ranges, const double *bg,
+                 double *img, double *final_T, int32_t *n_contrib, int32_t *flags, uint64_t *dhash)
+{
+    return blend_tiled(n, W, H, m, conic, amax, rgb, NULL, values, ranges, bg, img, NULL, final_T, n_contrib,
+                       flags, dhash);
+}
+
+/* The blend with the optical flow of Sec. 3.3 (md planar [2][n]; flow [2][H][W]). */
+int64_t oc_blend_flow(int n, int W, int H, const double *m, const double *conic, const double *amax,
+                      const double *rgb, const double *md, const uint32_t *values, const uint32_t *ranges,
+                      const double *bg, double *img, double *flow, double *final_T, int32_t *n_contrib,
+                      int32_t *flags)
+{
+    return blend_tiled(n, W, H, m, conic, amax, rgb, md, values, ranges, bg, img, flow, final_T, n_contrib,
+                       flags, NULL);
 }
 
 /* ---------------- blending (O0: brute force per pixel, tiny scenes) ----------------
@@ -344,8 +365,8 @@ void oc_blend_bruteforce(int n, int W, int H, const double *m, const double *con
             double out[3], T;
             int nc, fl;
             int64_t ne = 0;
-            blend_pixel_f64(n, m, conic, amax, rgb, list, len, px + 0.5, py + 0.5, bg, out, &T, &nc, &fl, &ne,
-                            NULL);
+            blend_pixel_f64(n, m, conic, amax, rgb, NULL, list, len, px + 0.5, py + 0.5, bg, out, NULL, &T, &nc,
+                            &fl, &ne, NULL);
             size_t pi = (size_t)py * W + px;
             for (int c = 0; c < 3; ++c) img[(size_t)c * W * H + pi] = out[c];
             if (final_T) final_T[pi] = T;
@@ -357,7 +378,9 @@ void oc_blend_bruteforce(int n, int W, int H, const double *m, const double *con
 }
 
 /* ---------------- blend adjoint ----------------
- * For pixel colour C = sum_i c_i a_i T_i + T_N bg with T_i = prod_{j<i} (1 - a_j):
+ * For pixel colour C = sum_i c_i a_i T_i + T_N bg with T_i = prod_{j<i} (1 - a_j)
+ * (and, with md / dL_dflow given, the flow F = sum_i md_i a_i T_i as two more channels
+ * of "colour" md_i and background 0):
  *   dC/dc_i = a_i T_i,
  *   dC/da_i = c_i T_i - (sum_{j>i} c_j a_j T_j + T_N bg) / (1 - a_i),
  *   a_i = amax_i exp(power_i) unless clamped to 0.99 (then constant),
@@ -366,19 +389,20 @@ void oc_blend_bruteforce(int n, int W, int H, const double *m, const double *con
  * directly.  Gradients are accumulated per Gaussian over all pixels.
  * Optionally reports the largest relative gap between the stored transmittance
  * and one recovered backwards by division, T_i = T_{i+1} / (1 - a_i).          */
-void oc_blend_bwd(int n, int W, int H, const double *m, const double *conic, const double *amax,
-                  const double *rgb, const uint32_t *values, const uint32_t *ranges, const double *bg,
-                  const double *dL_dimg, double *g_m, double *g_conic, double *g_amax, double *g_rgb,
-                  double *replay_rel_err)
+void oc_blend_bwd_flow(int n, int W, int H, const double *m, const double *conic, const double *amax,
+                       const double *rgb, const double *md, const uint32_t *values, const uint32_t *ranges,
+                       const double *bg, const double *dL_dimg, const double *dL_dflow, double *g_m,
+                       double *g_conic, double *g_amax, double *g_rgb, double *g_md, double *replay_rel_err)
 {
     int TX = (W + 15) / 16, TY = (H + 15) / 16;
     int nth = omp_get_max_threads();
-    double *acc = calloc((size_t)nth * 9 * (n > 0 ? n : 1), sizeof(double));
+    const int flow = md != NULL && dL_dflow != NULL;
+    double *acc = calloc((size_t)nth * 11 * (n > 0 ? n : 1), sizeof(double));
     double *errs = calloc((size_t)nth, sizeof(double));
 #pragma omp parallel
     {
         int tid = omp_get_thread_num();
-        double *a9 = acc + (size_t)tid * 9 * n;
+        double *a9 = acc + (size_t)tid * 11 * n;  /* m(2) conic(3) amax rgb(3) md(2) */
         size_t cap = 1024;
         uint32_t *gl = malloc(cap * sizeof(uint32_t));
         double *al = malloc(cap * sizeof(double)), *Tl = malloc(cap * sizeof(double));
@@ -399,8 +423,10 @@ void oc_blend_bwd(int n, int W, int H, const double *m, const double *conic, con
             for (int py = ty * 16; py < ty * 16 + 16 && py < H; ++py)
                 for (int px = tx * 16; px < tx * 16 + 16 && px < W; ++px) {
                     size_t pi = (size_t)py * W + px;
-                    double gC[3];
+                    double gC[3], gF[2] = {0.0, 0.0};
                     for (int c = 0; c < 3; ++c) gC[c] = dL_dimg[(size_t)c * W * H + pi];
+                    if (flow)
+                        for (int c = 0; c < 2; ++c) gF[c] = dL_dflow[(size_t)c * W * H + pi];
                     /* forward, storing every blended entry */
                     double T = 1.0, sx = px + 0.5, sy = py + 0.5;
                     int cnt = 0;
@@ -424,7 +450,7 @@ void oc_blend_bwd(int n, int W, int H, const double *m, const double *conic, con
                     }
                     double TN = T;
                     /* suffix sums S_i = sum_{j>i} c_j a_j T_j + T_N bg, per channel */
-                    double S[3];
+                    double S[3], SF[2] = {0.0, 0.0};
                     for (int c = 0; c < 3; ++c) S[c] = TN * bg[c];
                     double Trec = TN;
                     for (int i = cnt - 1; i >= 0; --i) {
@@ -441,6 +467,14 @@ void oc_blend_bwd(int n, int W, int H, const double *m, const double *conic, con
                             dC_da += gC[c] * (cc * Ti - S[c] / (1.0 - alpha));
                         }
                         for (int c = 0; c < 3; ++c) S[c] += rgb[c * n + g] * alpha * Ti;
+                        if (flow) {
+                            for (int c = 0; c < 2; ++c) {
+                                double f = md[c * n + g];
+                                a9[(9 + c) * n + g] += gF[c] * alpha * Ti;
+                                dC_da += gF[c] * (f * Ti - SF[c] / (1.0 - alpha));
+                            }
+                            for (int c = 0; c < 2; ++c) SF[c] += md[c * n + g] * alpha * Ti;
+                        }
                         if (cl[i]) continue;
                         double dpower = dC_da * alpha;
                         a9[5 * n + g] += dC_da * Gl[i];
@@ -457,8 +491,10 @@ void oc_blend_bwd(int n, int W, int H, const double *m, const double *conic, con
         free(gl); free(al); free(Tl); free(Gl); free(cl); free(dxl); free(dyl);
     }
     for (int t = 0; t < nth; ++t) {
-        const double *a9 = acc + (size_t)t * 9 * n;
+        const double *a9 = acc + (size_t)t * 11 * n;
         for (int g = 0; g < n; ++g) {
+            if (g_md)
+                for (int c = 0; c < 2; ++c) g_md[c * n + g] += a9[(9 + c) * n + g];
             g_m[g] += a9[g];
             g_m[n + g] += a9[n + g];
             g_conic[g] += a9[2 * n + g];
@@ -473,6 +509,15 @@ void oc_blend_bwd(int n, int W, int H, const double *m, const double *conic, con
     free(errs);
 }
 
+void oc_blend_bwd(int n, int W, int H, const double *m, const double *conic, const double *amax,
+                  const double *rgb, const uint32_t *values, const uint32_t *ranges, const double *bg,
+                  const double *dL_dimg, double *g_m, double *g_conic, double *g_amax, double *g_rgb,
+                  double *replay_rel_err)
+{
+    oc_blend_bwd_flow(n, W, H, m, conic, amax, rgb, NULL, values, ranges, bg, dL_dimg, NULL, g_m, g_conic, g_amax,
+                      g_rgb, NULL, replay_rel_err);
+}
+
 /* ---------------- projection adjoint by the complex-step method ----------------
  * For every Gaussian with active[g] != 0 and every parameter j, the projection is
  * evaluated with parameter j displaced by i*h; Im(output)/h is the exact partial
@@ -480,9 +525,9 @@ void oc_blend_bwd(int n, int W, int H, const double *m, const double *conic, con
  * part, i.e. are held fixed).  The splat-level gradients (m, conic, amax, rgb) are
  * contracted with these partials.  g_prm is planar [16+3K][n] in the parameter
  * order mu(3), s(3), q(4), o, mu_t, s_t, v(3), sh(k-major, rgb-minor).          */
-void oc_project_bwd(const oc_scene *s, const oc_camera *cam, double t, const int32_t *active,
-                    const double *g_m, const double *g_conic, const double *g_amax, const double *g_rgb,
-                    double *g_prm)
+void oc_project_bwd_flow(const oc_scene *s, const oc_camera *cam, double t, const int32_t *active,
+                         const double *g_m, const double *g_conic, const double *g_amax, const double *g_rgb,
+                         const double *g_md, double *g_prm)
 {
     int n = s->n, P = n_params(s->sh_degree);
     const double h = 1e-30;
@@ -505,9 +550,17 @@ void oc_project_bwd(const oc_scene *s, const oc_camera *cam, double t, const int
             for (int i = 0; i < 3; ++i) d += g_conic[i * n + g] * cimag(r.conic[i]) / h;
             d += g_amax[g] * cimag(r.amax) / h;
             for (int c = 0; c < 3; ++c) d += g_rgb[c * n + g] * cimag(r.rgb[c]) / h;
+            if (g_md) d += g_md[g] * cimag(r.md[0]) / h + g_md[n + g] * cimag(r.md[1]) / h;
             g_prm[(size_t)j * n + g] = d;
         }
     }
+}
+
+void oc_project_bwd(const oc_scene *s, const oc_camera *cam, double t, const int32_t *active,
+                    const double *g_m, const double *g_conic, const double *g_amax, const double *g_rgb,
+                    double *g_prm)
+{
+    oc_project_bwd_flow(s, cam, t, active, g_m, g_conic, g_amax, g_rgb, NULL, g_prm);
 }
 
 /* Spherical-harmonic basis at given unit directions (pins of the basis). */
