@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define D4DGS_ABI_VERSION 1
+#define D4DGS_ABI_VERSION 2
 #define D4DGS_TILE 16           /* tile edge in pixels */
 #define D4DGS_CAM_REC_FLOATS 19 /* camera-stage record: p3 u3 covc6 m0_2 md2 rgb3 */
 #define D4DGS_REC_FLOATS 12     /* splat record, 3 x float4 per Gaussian */
@@ -123,13 +123,17 @@ typedef struct {
  *   count  [n] uint32 tiles touched (0 = culled).
  *   offset [n] uint32 exclusive prefix of count (written by d4dgs_bin_sort).
  *   partial [ceil(capacity / 256)] uint32 scratch: per-block sums of count written by
- *          d4dgs_project and turned into block offsets by d4dgs_bin_sort. */
+ *          d4dgs_project and turned into block offsets by d4dgs_bin_sort.
+ *   mdot   [n][2] floats, optional (NULL: not written): the screen-space velocity of
+ *          the 2D mean, dm/dt = f u_xy / p_z in pixels per unit of t (Eq. 13), for
+ *          Gaussians with count > 0.  Needed by the flow render and its adjoint. */
 typedef struct {
     int32_t capacity;
     float *rec;
     uint32_t *count;
     uint32_t *offset;
     uint32_t *partial;
+    float *mdot;
 } d4dgs_splats;
 
 /* Sorted tile lists written by d4dgs_bin_sort (all device, caller-owned).
@@ -209,6 +213,40 @@ d4dgs_status d4dgs_render_bwd(const d4dgs_scene *scene, const d4dgs_camera *cam,
                               const d4dgs_splats *splats, const d4dgs_bins *bins, const float bg[3],
                               const float *final_T, const uint32_t *n_contrib, const float *dL_dimg,
                               float *inst_grads, d4dgs_grads *grads, d4dgs_stream stream);
+
+/* Optical flow (Sec. 3.3): as d4dgs_render_fwd, and also blends each splat's screen
+ * velocity splats->mdot with the colour weights, F = sum_i mdot_i alpha_i T_i (zero
+ * behind the last splat), into flow (device) [2][height][width].  splats->mdot must be
+ * set and written by d4dgs_project. */
+d4dgs_status d4dgs_render_fwd_flow(const d4dgs_splats *splats, const d4dgs_bins *bins, int32_t width,
+                                   int32_t height, const float bg[3], float *img, float *flow, float *final_T,
+                                   uint32_t *n_contrib, d4dgs_stream stream);
+
+/* Bytes of scratch d4dgs_flow_loss needs for a width x height image. */
+d4dgs_status d4dgs_flow_loss_workspace_size(int32_t width, int32_t height, size_t *bytes);
+
+/* Flow-gradient guided consistency loss (Sec. 3.3, Eq. 16-17) of a rendered image
+ * img [3][H][W] and flow [2][H][W] (device):
+ *   M = sqrt(u^2 + v^2 + eps); |grad M|, |grad I| by 3x3 Sobel filters over the pixels
+ *   whose 3x3 neighbourhood lies in the image (N of them; |grad I| over the three
+ *   channels: sqrt(sum_c Gx_c^2 + Gy_c^2)); each divided by its maximum over those
+ *   pixels, floored at 1e-6: nM, nI;  L = lambda / N * sum nM (1 - nI).
+ * Writes *loss (device float).  If dL_dflow (device [2][H][W]) is not NULL, also writes
+ * the gradient of L with respect to the flow, taking the edge weight (1 - nI) and both
+ * normalisers as constants (the loss shapes the motion).  Deterministic.  workspace:
+ * d4dgs_flow_loss_workspace_size bytes (device, no initialisation needed). */
+d4dgs_status d4dgs_flow_loss(const float *img, const float *flow, int32_t width, int32_t height, float lambda,
+                             float eps, void *workspace, size_t workspace_bytes, float *loss, float *dL_dflow,
+                             d4dgs_stream stream);
+
+/* Adjoint of d4dgs_project + d4dgs_render_fwd_flow: as d4dgs_render_bwd, with the
+ * upstream gradient of the flow dL_dflow (device [2][height][width]) as well;
+ * splats->mdot must hold the projection's screen velocities. */
+d4dgs_status d4dgs_render_bwd_flow(const d4dgs_scene *scene, const d4dgs_camera *cam, float t,
+                                   const d4dgs_splats *splats, const d4dgs_bins *bins, const float bg[3],
+                                   const float *final_T, const uint32_t *n_contrib, const float *dL_dimg,
+                                   const float *dL_dflow, float *inst_grads, d4dgs_grads *grads,
+                                   d4dgs_stream stream);
 
 /* Fixed-viewpoint multi-timestamp rendering: the parallel rendering of several frames of
  * one camera that the paper reports (Sec. 4, rendering speed), through Alg. 1 with the

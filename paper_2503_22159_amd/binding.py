@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libd4dgs.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 TILE = 16
 CAM_REC_FLOATS = 19
 REC_FLOATS = 12
@@ -46,7 +46,7 @@ class CamCache(C.Structure):
 
 class Splats(C.Structure):
     _fields_ = [("capacity", C.c_int32), ("rec", C.c_void_p), ("count", C.c_void_p), ("offset", C.c_void_p),
-                ("partial", C.c_void_p)]
+                ("partial", C.c_void_p), ("mdot", C.c_void_p)]
 
 
 class Bins(C.Structure):
@@ -83,7 +83,8 @@ class D4Error(RuntimeError):
 EXPORTS = ("d4dgs_abi_version", "d4dgs_last_error", "d4dgs_workspace_size", "d4dgs_project", "d4dgs_bin_sort",
            "d4dgs_bin_sort_sync", "d4dgs_render_fwd", "d4dgs_render_bwd", "d4dgs_serve_create",
            "d4dgs_serve_submit", "d4dgs_serve_poll", "d4dgs_serve_wait", "d4dgs_serve_stats_get",
-           "d4dgs_serve_destroy", "d4dgs_render_times")
+           "d4dgs_serve_destroy", "d4dgs_render_times", "d4dgs_render_fwd_flow", "d4dgs_flow_loss_workspace_size",
+           "d4dgs_flow_loss", "d4dgs_render_bwd_flow")
 
 
 def _load():
@@ -115,6 +116,13 @@ def _load():
                                          C.POINTER(CamCache), C.POINTER(Splats), C.POINTER(Bins),
                                          C.POINTER(C.c_void_p), C.c_size_t, C.POINTER(C.c_float * 3),
                                          C.POINTER(C.c_void_p), P, P]),
+        "d4dgs_render_fwd_flow": (C.c_int, [C.POINTER(Splats), C.POINTER(Bins), C.c_int32, C.c_int32,
+                                            C.POINTER(C.c_float * 3), P, P, P, P, P]),
+        "d4dgs_flow_loss_workspace_size": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+        "d4dgs_flow_loss": (C.c_int, [P, P, C.c_int32, C.c_int32, C.c_float, C.c_float, P, C.c_size_t, P, P, P]),
+        "d4dgs_render_bwd_flow": (C.c_int, [C.POINTER(Scene), C.POINTER(Camera), C.c_float, C.POINTER(Splats),
+                                            C.POINTER(Bins), C.POINTER(C.c_float * 3), P, P, P, P, P,
+                                            C.POINTER(Grads), P]),
     }
     for name, (res, args) in sig.items():
         try:

@@ -169,7 +169,7 @@ d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, fl
         }
     }
     const hipError_t e = launch_project(sk, ck, t, mode, crec, ccap, (float4 *)splats->rec, splats->count,
-                                        splats->partial, (hipStream_t)stream);
+                                        splats->partial, (float2 *)splats->mdot, (hipStream_t)stream);
     if (e != hipSuccess) {
         if (cache) cache->valid = 0;
         return hip_status(e, "d4dgs_project");
@@ -246,28 +246,100 @@ d4dgs_status d4dgs_render_fwd(const d4dgs_splats *splats, const d4dgs_bins *bins
     return hip_status(e, "d4dgs_render_fwd");
 }
 
-d4dgs_status d4dgs_render_bwd(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, const d4dgs_splats *splats,
-                              const d4dgs_bins *bins, const float bg[3], const float *final_T,
-                              const uint32_t *n_contrib, const float *dL_dimg, float *inst_grads, d4dgs_grads *grads,
-                              d4dgs_stream stream) {
+}  // extern "C"
+
+namespace {
+
+d4dgs_status render_bwd_impl(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, const d4dgs_splats *splats,
+                             const d4dgs_bins *bins, const float bg[3], const float *final_T,
+                             const uint32_t *n_contrib, const float *dL_dimg, const float *dL_dflow,
+                             float *inst_grads, d4dgs_grads *grads, d4dgs_stream stream) {
     D4_TRY(check_scene(scene));
     D4_TRY(check_camera(cam));
     D4_TRY(check_splats(splats, scene->n));
     D4_TRY(check_bins(bins));
     if (!bg || !final_T || !n_contrib || !dL_dimg || !inst_grads || !grads)
         return fail(D4DGS_ERR_INVALID_ARG, "render_bwd: NULL argument");
+    if (dL_dflow && scene->n > 0 && !splats->mdot)
+        return fail(D4DGS_ERR_INVALID_ARG, "render_bwd_flow: splats->mdot is NULL");
     if (scene->n > 0 && (!grads->mean || !grads->scale || !grads->quat || !grads->opacity || !grads->t_mean ||
                          !grads->t_scale || !grads->velocity || !grads->sh))
         return fail(D4DGS_ERR_INVALID_ARG, "render_bwd: gradient array is NULL");
     const SceneK sk = make_scenek(*scene);
     const CamK ck = make_camk(*cam);
     hipError_t e = launch_blend_bwd((const float4 *)splats->rec, splats->offset, bins->values, bins->ranges, ck, bg,
-                                    final_T, n_contrib, dL_dimg, (float4 *)inst_grads, bins->capacity,
-                                    (hipStream_t)stream);
+                                    final_T, n_contrib, dL_dimg, dL_dflow ? (const float2 *)splats->mdot : nullptr,
+                                    dL_dflow, (float4 *)inst_grads, bins->capacity, (hipStream_t)stream);
     if (e == hipSuccess)
         e = launch_project_bwd(sk, ck, t, (const float4 *)splats->rec, splats->count, splats->offset,
                                (const float4 *)inst_grads, bins->capacity, *grads, (hipStream_t)stream);
     return hip_status(e, "d4dgs_render_bwd");
+}
+
+}  // namespace
+
+extern "C" {
+
+d4dgs_status d4dgs_render_bwd(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, const d4dgs_splats *splats,
+                              const d4dgs_bins *bins, const float bg[3], const float *final_T,
+                              const uint32_t *n_contrib, const float *dL_dimg, float *inst_grads, d4dgs_grads *grads,
+                              d4dgs_stream stream) {
+    return render_bwd_impl(scene, cam, t, splats, bins, bg, final_T, n_contrib, dL_dimg, nullptr, inst_grads, grads,
+                           stream);
+}
+
+d4dgs_status d4dgs_render_bwd_flow(const d4dgs_scene *scene, const d4dgs_camera *cam, float t,
+                                   const d4dgs_splats *splats, const d4dgs_bins *bins, const float bg[3],
+                                   const float *final_T, const uint32_t *n_contrib, const float *dL_dimg,
+                                   const float *dL_dflow, float *inst_grads, d4dgs_grads *grads,
+                                   d4dgs_stream stream) {
+    if (!dL_dflow) return fail(D4DGS_ERR_INVALID_ARG, "render_bwd_flow: dL_dflow is NULL");
+    return render_bwd_impl(scene, cam, t, splats, bins, bg, final_T, n_contrib, dL_dimg, dL_dflow, inst_grads, grads,
+                           stream);
+}
+
+d4dgs_status d4dgs_render_fwd_flow(const d4dgs_splats *splats, const d4dgs_bins *bins, int32_t width,
+                                   int32_t height, const float bg[3], float *img, float *flow, float *final_T,
+                                   uint32_t *n_contrib, d4dgs_stream stream) {
+    if (!splats || !splats->rec) return fail(D4DGS_ERR_INVALID_ARG, "splats is NULL");
+    if (!splats->mdot) return fail(D4DGS_ERR_INVALID_ARG, "render_fwd_flow: splats->mdot is NULL");
+    D4_TRY(check_bins(bins));
+    if (width <= 0 || height <= 0 || width > 65535 * kTile || height > 65535 * kTile)
+        return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
+    if (!bg || !img || !flow) return fail(D4DGS_ERR_INVALID_ARG, "bg, img or flow is NULL");
+    if ((final_T == nullptr) != (n_contrib == nullptr))
+        return fail(D4DGS_ERR_INVALID_ARG, "final_T and n_contrib must both be given or both be NULL");
+    d4dgs_camera dummy;
+    std::memset(&dummy, 0, sizeof(dummy));
+    dummy.width = width;
+    dummy.height = height;
+    const CamK ck = make_camk(dummy);
+    const hipError_t e = launch_blend_flow((const float4 *)splats->rec, (const float2 *)splats->mdot, bins->values,
+                                           bins->ranges, ck, bg, img, flow, final_T, n_contrib, (hipStream_t)stream);
+    return hip_status(e, "d4dgs_render_fwd_flow");
+}
+
+d4dgs_status d4dgs_flow_loss_workspace_size(int32_t width, int32_t height, size_t *bytes) {
+    if (!bytes) return fail(D4DGS_ERR_INVALID_ARG, "bytes is NULL");
+    if (width <= 0 || height <= 0 || (int64_t)width * height > (int64_t)1 << 30)
+        return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
+    *bytes = flow_loss_workspace_bytes(width, height);
+    return D4DGS_OK;
+}
+
+d4dgs_status d4dgs_flow_loss(const float *img, const float *flow, int32_t width, int32_t height, float lambda,
+                             float eps, void *workspace, size_t workspace_bytes, float *loss, float *dL_dflow,
+                             d4dgs_stream stream) {
+    if (!img || !flow || !workspace || !loss) return fail(D4DGS_ERR_INVALID_ARG, "flow_loss: NULL argument");
+    if (width <= 0 || height <= 0 || (int64_t)width * height > (int64_t)1 << 30)
+        return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
+    if (!std::isfinite(lambda) || !std::isfinite(eps) || eps < 0.0f)
+        return fail(D4DGS_ERR_INVALID_ARG, "flow_loss: lambda must be finite and eps finite and >= 0");
+    if (workspace_bytes < flow_loss_workspace_bytes(width, height))
+        return fail(D4DGS_ERR_OUT_OF_MEMORY, "workspace smaller than d4dgs_flow_loss_workspace_size");
+    const hipError_t e =
+        launch_flow_loss(img, flow, width, height, lambda, eps, workspace, loss, dL_dflow, (hipStream_t)stream);
+    return hip_status(e, "d4dgs_flow_loss");
 }
 
 // Streams and events of d4dgs_render_times, one set per device, created on first use

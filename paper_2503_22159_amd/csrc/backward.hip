@@ -67,6 +67,15 @@ __device__ __forceinline__ float sum_xor32(float v) {
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// Wavefront total of y, in every lane.
+__device__ __forceinline__ float wave_allsum(float y) {
+    y += dpp_move<kDppXor1>(y);
+    y += dpp_move<kDppXor2>(y);
+    y += dpp_move<kDppRor4>(y);
+    y += dpp_move<kDppRor8>(y);
+    return sum_xor32(sum_xor16(y));
+}
+
 // Which of the eight reduce-scattered values lane l holds after wave_sum9.
 __device__ __forceinline__ int red_index(int l) { return 4 * (l & 1) + 2 * ((l >> 1) & 1) + ((l >> 2) & 1); }
 
@@ -96,14 +105,12 @@ __device__ __forceinline__ void wave_sum9(const float v[9], float &x, float &y) 
     }
     x += dpp_move<kDppRor8>(x);
     x = sum_xor32(sum_xor16(x));
-    y = v[8];
-    y += dpp_move<kDppXor1>(y);
-    y += dpp_move<kDppXor2>(y);
-    y += dpp_move<kDppRor4>(y);
-    y += dpp_move<kDppRor8>(y);
-    y = sum_xor32(sum_xor16(y));
+    y = wave_allsum(v[8]);
 }
 
+// FLOW: the flow F = sum mdot alpha T (background 0) is two more colour channels with
+// upstream gradient dLf; their colour gradients dL/dmdot go to the slot's third float4.
+template <bool FLOW>
 __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ rec,
                                                      const uint32_t *__restrict__ offset,
                                                      const uint32_t *__restrict__ vals,
@@ -111,7 +118,10 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
                                                      float bg1, float bg2, const float *__restrict__ final_T,
                                                      const uint32_t *__restrict__ ncontrib,
                                                      const float *__restrict__ dL, float4 *__restrict__ ig,
-                                                     uint32_t capacity, int ntiles, int per_xcd) {
+                                                     uint32_t capacity, int ntiles, int per_xcd,
+                                                     const float2 *__restrict__ mdot,
+                                                     const float *__restrict__ dLf) {
+    constexpr int NR = FLOW ? 11 : 9;  // sums reduced per splat
     const int b = blockIdx.x;
     const int tile = (b & 7) * per_xcd + (b >> 3);
     if (tile >= ntiles) return;
@@ -122,7 +132,7 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
     // pixel centres: (ox + 0..15, oy + 0..15)
     const float ox = (float)(tx * kTile) + 0.5f, oy = (float)(ty * kTile) + 0.5f;
     const float sx = ox + (float)lxi;
-    float sy[kPx], Tc[kPx], GS[kPx], g0[kPx], g1[kPx], g2[kPx];
+    float sy[kPx], Tc[kPx], GS[kPx], g0[kPx], g1[kPx], g2[kPx], g3[kPx], g4[kPx];
     uint32_t nc[kPx];
     uint32_t nmax = 0;
 #pragma unroll
@@ -137,6 +147,8 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
         g0[k] = in ? dL[pi] : 0.0f;
         g1[k] = in ? dL[plane + pi] : 0.0f;
         g2[k] = in ? dL[2 * plane + pi] : 0.0f;
+        g3[k] = FLOW && in ? dLf[pi] : 0.0f;
+        g4[k] = FLOW && in ? dLf[plane + pi] : 0.0f;
         GS[k] = Tc[k] * (g0[k] * bg0 + g1[k] * bg1 + g2[k] * bg2);
         nmax = max(nmax, nc[k]);
     }
@@ -150,7 +162,8 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
     }
     // s2 = {b, bits(plain << 31 | list position), bits(slot), amax}, s3 = {conic a, b, c, -}
     __shared__ float4 s0[kWave], s1[kWave], s2[kWave], s3[kWave];
-    __shared__ float red[kWave * 9];
+    __shared__ float2 s4[FLOW ? kWave : 1];  // mdot
+    __shared__ float red[kWave * NR];
     const float wx1 = ox + (float)(kTile - 1), wy1 = oy + (float)(kTile - 1);
     // batches of 64 list entries, last batch first
     for (uint32_t jb = start + nmax; jb > start;) {
@@ -158,6 +171,7 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
         const uint32_t j = j0 + ln;
         bool keep = false, plain = false;
         float4 f0, f1, f2, r0, r1;
+        float2 fm = make_float2(0.f, 0.f);
         uint32_t slot = 0;
         if (j < jb) {
             const uint32_t gi = vals[j];
@@ -166,6 +180,7 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
             const float4 r2 = rec[3 * (size_t)gi + 2];
             fold_raw(r0, r1, r2, f0, f1, f2);
             slot = inst_slot(r2, offset[gi], tx, ty);
+            if (FLOW) fm = mdot[gi];
             keep = !splat_misses(f0, f2, ox, wx1, oy, wy1);
             plain = splat_plain(r0, r1);
             if (!keep && slot < capacity) zero_slot(ig, slot);  // no pixel of the tile reaches 1/255
@@ -179,6 +194,7 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
             s2[pos] = make_float4(f2.x, __uint_as_float((plain ? 0x80000000u : 0u) | (j - start)),
                                   __uint_as_float(slot), r1.y);
             s3[pos] = make_float4(r0.z, r0.w, r1.x, 0.0f);
+            if (FLOW) s4[pos] = fm;
         }
         __syncthreads();
         const int nb = __popcll(km);
@@ -191,7 +207,8 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
             const uint64_t pos_ok = (tag >> 31) ? ~0ull : 0ull;
             const float dx = sx - h0.x;
             const ColTerms ct = col_terms(h0, h1, dx);
-            float d0 = 0.f, e1 = 0.f, e2 = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
+            float d0 = 0.f, e1 = 0.f, e2 = 0.f, ar = 0.f, ag = 0.f, ab = 0.f, af0 = 0.f, af1 = 0.f;
+            const float2 h4 = FLOW ? s4[i] : make_float2(0.f, 0.f);
 #pragma unroll
             for (int k = 0; k < kPx; ++k) {
                 const float dy = sy[k] - h0.y;
@@ -204,13 +221,18 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
                 const bool unclamped = __builtin_amdgcn_inverse_ballot_w64(ok & __ballot(e <= kAlphaMax));
                 const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
                 const float Ti = Tc[k] * inv;  // transmittance in front of this splat
-                const float gc = __builtin_fmaf(g2[k], h2.x, __builtin_fmaf(g1[k], h1.w, g0[k] * h1.z));
+                float gc = __builtin_fmaf(g2[k], h2.x, __builtin_fmaf(g1[k], h1.w, g0[k] * h1.z));
+                if (FLOW) gc = __builtin_fmaf(g4[k], h4.y, __builtin_fmaf(g3[k], h4.x, gc));
                 const float wgt = okb ? alpha * Ti : 0.0f;
                 const float da = __builtin_fmaf(-inv, GS[k], Ti * gc);
                 GS[k] = __builtin_fmaf(gc, wgt, GS[k]);
                 ar = __builtin_fmaf(g0[k], wgt, ar);
                 ag = __builtin_fmaf(g1[k], wgt, ag);
                 ab = __builtin_fmaf(g2[k], wgt, ab);
+                if (FLOW) {
+                    af0 = __builtin_fmaf(g3[k], wgt, af0);
+                    af1 = __builtin_fmaf(g4[k], wgt, af1);
+                }
                 Tc[k] = okb ? Ti : Tc[k];
                 // d/d(power); zero where alpha is clamped (alpha = amax exp(power) otherwise)
                 const float dp = unclamped ? da * alpha : 0.0f;
@@ -222,21 +244,28 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ 
             const float v[9] = {d0, dx * d0, e1, (dx * dx) * d0, dx * e1, e2, ar, ag, ab};
             float x, y;
             wave_sum9(v, x, y);
-            if (ln < 9) red[9 * i + (ln < 8 ? red_index(ln) : 8)] = ln < 8 ? x : y;
+            if (ln < 9) red[NR * i + (ln < 8 ? red_index(ln) : 8)] = ln < 8 ? x : y;
+            if (FLOW) {
+                const float f0 = wave_allsum(af0), f1 = wave_allsum(af1);
+                if (ln == 0) {
+                    red[NR * i + 9] = f0;
+                    red[NR * i + 10] = f1;
+                }
+            }
         }
         __syncthreads();
         // one lane per kept splat: moments -> gradients of the 2D mean (d power / d m =
         // Q d), the conic (-d d^T / 2, off-diagonal -dx dy) and amax (alpha / amax per
         // unclamped pixel)
         if (ln < nb) {
-            const float *m = &red[9 * ln];
+            const float *m = &red[NR * ln];
             const float P0 = m[0], Sx = m[1], Sy = m[2], Sxx = m[3], Sxy = m[4], Syy = m[5];
             const float4 h2 = s2[ln], h3 = s3[ln];
             const uint32_t sl = __float_as_uint(h2.z);
             if (sl < capacity) {
                 ig[3 * (size_t)sl + 0] = make_float4(h3.x * Sx + h3.y * Sy, h3.z * Sy + h3.y * Sx, -0.5f * Sxx, -Sxy);
                 ig[3 * (size_t)sl + 1] = make_float4(-0.5f * Syy, P0 / h2.w, m[6], m[7]);
-                ig[3 * (size_t)sl + 2] = make_float4(m[8], 0.f, 0.f, 0.f);
+                ig[3 * (size_t)sl + 2] = make_float4(m[8], FLOW ? m[9] : 0.f, FLOW ? m[10] : 0.f, 0.f);
             }
         }
         __syncthreads();
@@ -300,6 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     if ((uint64_t)offset[gi] + cnt > capacity) return;  // instances lost to an overflow
     // 1. sum this Gaussian's instance gradients in emission order
     float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gam = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
+    float gfx = 0.f, gfy = 0.f;  // dL/dmdot from the flow (zero when no flow was rendered)
     const uint32_t o0 = offset[gi];
     for (uint32_t k = 0; k < cnt; ++k) {
         const size_t sl = 3 * (size_t)(o0 + k);
@@ -307,6 +337,8 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
         gmx += a.x; gmy += a.y; gA += a.z; gB += a.w;
         gC += b4.x; gam += b4.y; gr += b4.z; gg += b4.w;
         gb += c4.x;
+        gfx += c4.y;
+        gfy += c4.z;
     }
     // 2. recompute the forward quantities (camera stage + time stage)
     const float q0 = s.quat[gi], q1 = s.quat[n + gi], q2 = s.quat[2 * n + gi], q3 = s.quat[3 * n + gi];
@@ -404,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     }
     g_tau += u[0] * g_pt[0] + u[1] * g_pt[1] + u[2] * g_pt[2];
     g_tau += md[0] * gmx + md[1] * gmy;
-    const float g_mdx = tau * gmx, g_mdy = tau * gmy;
+    const float g_mdx = tau * gmx + gfx, g_mdy = tau * gmy + gfy;
     // camera stage: m0 = f p_xy / p_z + c ; md = f u_xy / p_z
     const float ipz = 1.f / p[2];
     g_p[0] += c.fx * gmx * ipz;
@@ -488,12 +520,19 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
 
 hipError_t launch_blend_bwd(const float4 *rec, const uint32_t *offset, const uint32_t *vals, const uint32_t *ranges,
                             const CamK &c, const float bg[3], const float *final_T, const uint32_t *n_contrib,
-                            const float *dL_dimg, float4 *inst_grads, int64_t capacity, hipStream_t st) {
+                            const float *dL_dimg, const float2 *mdot, const float *dL_dflow, float4 *inst_grads,
+                            int64_t capacity, hipStream_t st) {
     const int ntiles = c.TX * c.TY;
     if (ntiles == 0) return hipSuccess;
     const int per_xcd = (ntiles + 7) / 8;
-    hipLaunchKernelGGL(k_blend_bwd, dim3(per_xcd * 8), dim3(kWave), 0, st, rec, offset, vals, ranges, c, bg[0], bg[1],
-                       bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, ntiles, per_xcd);
+    if (mdot && dL_dflow)
+        hipLaunchKernelGGL(k_blend_bwd<true>, dim3(per_xcd * 8), dim3(kWave), 0, st, rec, offset, vals, ranges, c,
+                           bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, ntiles,
+                           per_xcd, mdot, dL_dflow);
+    else
+        hipLaunchKernelGGL(k_blend_bwd<false>, dim3(per_xcd * 8), dim3(kWave), 0, st, rec, offset, vals, ranges, c,
+                           bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, ntiles,
+                           per_xcd, nullptr, nullptr);
     return hipGetLastError();
 }
 

@@ -32,11 +32,11 @@ namespace {
 // One splat against the lane's PX pixels.  PLAIN: the splat passed splat_plain, so the
 // "exponent > 0" skip and the 0.99 clamp cannot fire and are not evaluated.  Returns true
 // when every pixel of the wavefront is done.
-template <int PX, bool STATE, bool PLAIN>
-__device__ __forceinline__ bool blend_splat(const float4 &g0, const float4 &g1, float cb, uint32_t pos, float sx,
-                                            const float (&sy)[PX], float (&T)[PX], float (&C0)[PX],
-                                            float (&C1)[PX], float (&C2)[PX], uint64_t (&done)[PX],
-                                            uint32_t (&last)[PX]) {
+template <int PX, bool STATE, bool PLAIN, bool FLOW>
+__device__ __forceinline__ bool blend_splat(const float4 &g0, const float4 &g1, const float4 &g2, uint32_t pos,
+                                            float sx, const float (&sy)[PX], float (&T)[PX], float (&C0)[PX],
+                                            float (&C1)[PX], float (&C2)[PX], float (&F0)[PX], float (&F1)[PX],
+                                            uint64_t (&done)[PX], uint32_t (&last)[PX]) {
     const ColTerms ct = col_terms(g0, g1, sx - g0.x);
     uint64_t all = ~0ull;
 #pragma unroll
@@ -54,7 +54,11 @@ __device__ __forceinline__ bool blend_splat(const float4 &g0, const float4 &g1, 
         const float wgt = blend ? alpha * Tk : 0.0f;
         C0[k] = __builtin_fmaf(g1.z, wgt, C0[k]);
         C1[k] = __builtin_fmaf(g1.w, wgt, C1[k]);
-        C2[k] = __builtin_fmaf(cb, wgt, C2[k]);
+        C2[k] = __builtin_fmaf(g2.x, wgt, C2[k]);
+        if (FLOW) {
+            F0[k] = __builtin_fmaf(g2.z, wgt, F0[k]);
+            F1[k] = __builtin_fmaf(g2.w, wgt, F1[k]);
+        }
         T[k] = blend ? Tn : Tk;
         if (STATE) last[k] = blend ? pos : last[k];
         all &= done[k];
@@ -62,18 +66,19 @@ __device__ __forceinline__ bool blend_splat(const float4 &g0, const float4 &g1, 
     return all == ~0ull;
 }
 
-template <int PX, int RW, bool STATE>
+template <int PX, int RW, bool STATE, bool FLOW>
 __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                  const uint32_t *__restrict__ ranges, CamK c, float bg0, float bg1,
                                                  float bg2, float *__restrict__ img, float *__restrict__ final_T,
-                                                 uint32_t *__restrict__ ncontrib, int nlogical, int per_xcd) {
+                                                 uint32_t *__restrict__ ncontrib, int nlogical, int per_xcd,
+                                                 const float2 *__restrict__ mdot, float *__restrict__ flow) {
     constexpr int LR = kWave / RW;      // lane rows
     constexpr int RH = LR * PX;         // rows of the wavefront's pixel region (RW x RH)
     constexpr int NXR = kTile / RW;     // regions across a tile
     constexpr int WPT = 4 / PX;         // waves per tile
     static_assert(RH <= kTile && (RW == 8 || RW == 16), "wavefront region must tile a 16x16 tile");
-    // s2[i] = {b, bits(plain << 31 | list position + 1), -, -}: strided like s0 and s1 so
-    // that one address register serves all three reads
+    // s2[i] = {b, bits(plain << 31 | list position + 1), mdot.x, mdot.y}: strided like s0
+    // and s1 so that one address register serves all three reads
     __shared__ float4 s0[kWave], s1[kWave], s2[kWave];
     const int b = blockIdx.x;
     const int L = (b & 7) * per_xcd + (b >> 3);
@@ -87,7 +92,7 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     // pixel-centre box of this wavefront (for skipping splats that cannot reach it)
     const float wx0 = (float)rx0 + 0.5f, wx1 = wx0 + (float)(RW - 1);
     const float wy0 = (float)ry0 + 0.5f, wy1 = wy0 + (float)(RH - 1);
-    float sy[PX], T[PX], C0[PX], C1[PX], C2[PX];
+    float sy[PX], T[PX], C0[PX], C1[PX], C2[PX], F0[PX], F1[PX];
     uint64_t done[PX];
     uint32_t last[PX];
 #pragma unroll
@@ -96,17 +101,19 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
         sy[k] = (float)py + 0.5f;
         T[k] = 1.0f;
         done[k] = __ballot(!(px < c.W && py < c.H));
-        C0[k] = C1[k] = C2[k] = 0.0f;
+        C0[k] = C1[k] = C2[k] = F0[k] = F1[k] = 0.0f;
         last[k] = 0u;
     }
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     // software pipeline: list entries two batches ahead, records one batch ahead
     float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
+    float2 nm = make_float2(0.f, 0.f);
     if (start + ln < end) {
         const uint32_t g = vals[start + ln];
         n0 = rec[3 * (size_t)g];
         n1 = rec[3 * (size_t)g + 1];
         n2 = rec[3 * (size_t)g + 2];
+        if (FLOW) nm = mdot[g];
     }
     uint32_t gnext = start + kWave + ln < end ? vals[start + kWave + ln] : 0u;
     for (uint32_t j0 = start; j0 < end; j0 += kWave) {
@@ -127,14 +134,15 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
             s0[pos] = f0;
             s1[pos] = f1;
-            s2[pos].x = f2.x;
-            s2[pos].y = __uint_as_float((plain ? 0x80000000u : 0u) | (j0 - start + ln + 1));
+            s2[pos] = make_float4(f2.x, __uint_as_float((plain ? 0x80000000u : 0u) | (j0 - start + ln + 1)), nm.x,
+                                  nm.y);
         }
         __syncthreads();
         if (j0 + kWave + ln < end) {
             n0 = rec[3 * (size_t)gnext];
             n1 = rec[3 * (size_t)gnext + 1];
             n2 = rec[3 * (size_t)gnext + 2];
+            if (FLOW) nm = mdot[gnext];
         }
         if (j0 + 2 * kWave + ln < end) gnext = vals[j0 + 2 * kWave + ln];
         const int nb = __popcll(km);
@@ -142,17 +150,22 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
         // positive-exponent test and the clamp
         if (__ballot(keep && !plain) == 0) {
             for (int i = 0; i < nb; ++i) {
-                const float2 g2 = *reinterpret_cast<const float2 *>(&s2[i]);
+                const float4 g2 = FLOW ? s2[i] : make_float4(s2[i].x, s2[i].y, 0.f, 0.f);
                 const uint32_t pos = __float_as_uint(g2.y) & 0x7fffffffu;
-                if (blend_splat<PX, STATE, true>(s0[i], s1[i], g2.x, pos, sx, sy, T, C0, C1, C2, done, last)) break;
+                if (blend_splat<PX, STATE, true, FLOW>(s0[i], s1[i], g2, pos, sx, sy, T, C0, C1, C2, F0, F1, done,
+                                                       last))
+                    break;
             }
         } else {
             for (int i = 0; i < nb; ++i) {
-                const float2 g2 = *reinterpret_cast<const float2 *>(&s2[i]);
+                const float4 g2 = FLOW ? s2[i] : make_float4(s2[i].x, s2[i].y, 0.f, 0.f);
                 const uint32_t pos = __float_as_uint(g2.y) & 0x7fffffffu;
-                const bool fin = (__builtin_amdgcn_readfirstlane(__float_as_uint(g2.y)) >> 31)
-                                     ? blend_splat<PX, STATE, true>(s0[i], s1[i], g2.x, pos, sx, sy, T, C0, C1, C2, done, last)
-                                     : blend_splat<PX, STATE, false>(s0[i], s1[i], g2.x, pos, sx, sy, T, C0, C1, C2, done, last);
+                const bool fin =
+                    (__builtin_amdgcn_readfirstlane(__float_as_uint(g2.y)) >> 31)
+                        ? blend_splat<PX, STATE, true, FLOW>(s0[i], s1[i], g2, pos, sx, sy, T, C0, C1, C2, F0, F1,
+                                                             done, last)
+                        : blend_splat<PX, STATE, false, FLOW>(s0[i], s1[i], g2, pos, sx, sy, T, C0, C1, C2, F0, F1,
+                                                              done, last);
                 if (fin) break;
             }
         }
@@ -171,6 +184,10 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
             final_T[pi] = T[k];
             ncontrib[pi] = last[k];
         }
+        if (FLOW) {
+            flow[pi] = F0[k];
+            flow[plane + pi] = F1[k];
+        }
     }
 }
 
@@ -180,11 +197,12 @@ void launch_px(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, 
     const int nlogical = c.TX * c.TY * (4 / PX);
     const int per_xcd = (nlogical + 7) / 8;
     if (final_T)
-        hipLaunchKernelGGL((k_blend<PX, RW, true>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c,
-                           bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd);
+        hipLaunchKernelGGL((k_blend<PX, RW, true, false>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges,
+                           c, bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd, nullptr, nullptr);
     else
-        hipLaunchKernelGGL((k_blend<PX, RW, false>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c,
-                           bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd);
+        hipLaunchKernelGGL((k_blend<PX, RW, false, false>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals,
+                           ranges, c, bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd, nullptr,
+                           nullptr);
 }
 
 // Wavefront pixel region: PX pixels per lane in one column, RW columns wide.  Default 1 x 8
@@ -212,6 +230,21 @@ hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t 
         case 416: launch_px<4, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
         default: launch_px<1, 8>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_flow(const float4 *rec, const float2 *mdot, const uint32_t *vals, const uint32_t *ranges,
+                             const CamK &c, const float bg[3], float *img, float *flow, float *final_T,
+                             uint32_t *n_contrib, hipStream_t st) {
+    if (c.TX * c.TY == 0) return hipSuccess;
+    const int nlogical = c.TX * c.TY * 4;  // one pixel per lane, 8x8 squares
+    const int per_xcd = (nlogical + 7) / 8;
+    if (final_T)
+        hipLaunchKernelGGL((k_blend<1, 8, true, true>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c,
+                           bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd, mdot, flow);
+    else
+        hipLaunchKernelGGL((k_blend<1, 8, false, true>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges,
+                           c, bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd, mdot, flow);
     return hipGetLastError();
 }
 

@@ -153,7 +153,7 @@ SceneK make_scenek(const d4dgs_scene &s);
 
 // mode 0: camera + time stage, no record; 1: camera + time stage, writes record; 2: time stage from record
 hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, float *cam_rec, int cam_cap,
-                          float4 *rec, uint32_t *count, uint32_t *block_sums, hipStream_t st);
+                          float4 *rec, uint32_t *count, uint32_t *block_sums, float2 *mdot, hipStream_t st);
 
 // One request of a batched projection (kernel argument, by value).
 struct ReqK {
@@ -204,11 +204,20 @@ hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *o
 
 hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c,
                         const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st);
+// the blend with the optical flow: mdot [n] per splat, flow [2][H][W]
+hipError_t launch_blend_flow(const float4 *rec, const float2 *mdot, const uint32_t *vals, const uint32_t *ranges,
+                             const CamK &c, const float bg[3], float *img, float *flow, float *final_T,
+                             uint32_t *n_contrib, hipStream_t st);
 
+// mdot / dL_dflow NULL: colour only
 hipError_t launch_blend_bwd(const float4 *rec, const uint32_t *offset, const uint32_t *vals,
                             const uint32_t *ranges, const CamK &c, const float bg[3], const float *final_T,
-                            const uint32_t *n_contrib, const float *dL_dimg, float4 *inst_grads,
-                            int64_t capacity, hipStream_t st);
+                            const uint32_t *n_contrib, const float *dL_dimg, const float2 *mdot,
+                            const float *dL_dflow, float4 *inst_grads, int64_t capacity, hipStream_t st);
+
+size_t flow_loss_workspace_bytes(int W, int H);
+hipError_t launch_flow_loss(const float *img, const float *flow, int W, int H, float lambda, float eps, void *ws,
+                            float *loss, float *dL_dflow, hipStream_t st);
 
 hipError_t launch_project_bwd(const SceneK &s, const CamK &c, float t, const float4 *rec, const uint32_t *count,
                               const uint32_t *offset, const float4 *inst_grads, int64_t capacity,

@@ -224,7 +224,8 @@ __device__ __forceinline__ void store_rec(float4 *__restrict__ rec, int gi, cons
 template <int MODE, int DEG>
 __global__ __launch_bounds__(kBlock) void k_project(SceneK s, CamK c, float t, float *__restrict__ cam_rec,
                                                    int cap, float4 *__restrict__ rec,
-                                                   uint32_t *__restrict__ count, uint32_t *__restrict__ block_sums) {
+                                                   uint32_t *__restrict__ count, uint32_t *__restrict__ block_sums,
+                                                   float2 *__restrict__ mdot) {
     const int gi = blockIdx.x * kBlock + threadIdx.x;
     uint32_t cnt = 0;
     if (gi < s.n) {
@@ -282,7 +283,10 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneK s, CamK c, float t, f
         if (ok) {
             float4 r0, r1, r2;
             cnt = time_stage(cr, s.opacity[gi], s.t_mean[gi], s.t_scale[gi], t, c, r0, r1, r2);
-            if (cnt) store_rec(rec, gi, r0, r1, r2);
+            if (cnt) {
+                store_rec(rec, gi, r0, r1, r2);
+                if (mdot) mdot[gi] = make_float2(cr.md[0], cr.md[1]);  // dm/dt (Eq. 13)
+            }
         }
         count[gi] = cnt;
     }
@@ -403,12 +407,12 @@ __global__ __launch_bounds__(kBlock) void k_project_times(SceneK s, CamK c, floa
 }  // namespace
 
 hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, float *cam_rec, int cam_cap,
-                          float4 *rec, uint32_t *count, uint32_t *block_sums, hipStream_t st) {
+                          float4 *rec, uint32_t *count, uint32_t *block_sums, float2 *mdot, hipStream_t st) {
     if (s.n == 0) return hipSuccess;
     const int grid = (s.n + kBlock - 1) / kBlock;
 #define D4_LAUNCH(M, D)                                                                                  \
     hipLaunchKernelGGL((k_project<M, D>), dim3(grid), dim3(kBlock), 0, st, s, c, t, cam_rec, cam_cap, rec, \
-                       count, block_sums)
+                       count, block_sums, mdot)
     if (mode == 2) {
         D4_LAUNCH(2, 0);
     } else {

@@ -66,7 +66,7 @@ class DeviceScene:
 class FrameState:
     """Device buffers of one rendered frame (splat record, sorted bins, replay state)."""
 
-    def __init__(self, n, width, height, capacity, device="cuda"):
+    def __init__(self, n, width, height, capacity, device="cuda", flow=False):
         self.n, self.width, self.height, self.capacity = n, width, height, int(capacity)
         dev = device
         nn = max(n, 1)
@@ -80,6 +80,9 @@ class FrameState:
         self.num_inst = torch.zeros(1, dtype=torch.int64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.ws = torch.empty(B.workspace_size(n, width, height, self.capacity), dtype=torch.uint8, device=dev)
+        # screen velocity of each splat (written by the projection when the flow is wanted)
+        self.mdot = torch.empty(nn * 2, dtype=torch.float32, device=dev) if flow else None
+        self.flow = None
         self.img = None
         self.final_T = None
         self.n_contrib = None
@@ -90,6 +93,7 @@ class FrameState:
         s.capacity = max(self.n, 1)
         s.rec, s.count, s.offset, s.partial = (self.rec.data_ptr(), self.count.data_ptr(),
                                                self.offset.data_ptr(), self.partial.data_ptr())
+        s.mdot = self.mdot.data_ptr() if self.mdot is not None else None
         return s
 
     def bins(self):
@@ -180,8 +184,9 @@ def grads_like(scene: DeviceScene):
     return {k: torch.zeros_like(scene.t[k]) for k in FIELDS}
 
 
-def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, grads=None):
-    """Adds d(sum dL_dimg * img)/d(params) into `grads` (created zeroed if None)."""
+def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, grads=None, dL_dflow=None):
+    """Adds d(sum dL_dimg * img [+ sum dL_dflow * flow])/d(params) into `grads` (created
+    zeroed if None).  dL_dflow needs a frame rendered with the flow."""
     if grads is None:
         grads = grads_like(scene)
     dL = dL_dimg.contiguous().float()
@@ -191,10 +196,59 @@ def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, gra
     for k in FIELDS:
         setattr(g, k, grads[k].data_ptr())
     s = scene.struct()
-    B.check(B.lib.d4dgs_render_bwd(C.byref(s), C.byref(B.camera_struct(cam)), float(t), C.byref(st.splats()),
-                                   C.byref(st.bins()), C.byref(_bg(bg)), _ptr(st.final_T), _ptr(st.n_contrib),
-                                   _ptr(dL), _ptr(st.inst_grads), C.byref(g), _stream()))
+    if dL_dflow is None:
+        B.check(B.lib.d4dgs_render_bwd(C.byref(s), C.byref(B.camera_struct(cam)), float(t), C.byref(st.splats()),
+                                       C.byref(st.bins()), C.byref(_bg(bg)), _ptr(st.final_T), _ptr(st.n_contrib),
+                                       _ptr(dL), _ptr(st.inst_grads), C.byref(g), _stream()))
+    else:
+        dF = dL_dflow.contiguous().float()
+        B.check(B.lib.d4dgs_render_bwd_flow(C.byref(s), C.byref(B.camera_struct(cam)), float(t),
+                                            C.byref(st.splats()), C.byref(st.bins()), C.byref(_bg(bg)),
+                                            _ptr(st.final_T), _ptr(st.n_contrib), _ptr(dL), _ptr(dF),
+                                            _ptr(st.inst_grads), C.byref(g), _stream()))
     return grads
+
+
+def render_forward_flow(scene: DeviceScene, cam, t, bg=(0.0, 0.0, 0.0), capacity=None, keep_state=True,
+                        cache: CamCache | None = None):
+    """Forward render with the optical flow of Sec. 3.3 (each splat's screen velocity
+    blended with the colour weights).  Returns (img [3,H,W], flow [2,H,W], state)."""
+    cap = capacity or default_capacity(scene.n, cam.width, cam.height)
+    dev = scene.t["mean"].device
+    st = FrameState(scene.n, cam.width, cam.height, cap, dev, flow=True)
+    project(scene, cam, t, st, cache)
+    ni = bin_sort(st, sync=True)
+    if ni > st.capacity:
+        st = FrameState(scene.n, cam.width, cam.height, int(ni * 1.25) + 1024, dev, flow=True)
+        project(scene, cam, t, st, cache)
+        assert bin_sort(st, sync=True) == ni
+    st.num_instances = ni
+    H, W = cam.height, cam.width
+    st.img = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    st.flow = torch.empty((2, H, W), dtype=torch.float32, device=dev)
+    if keep_state:
+        st.final_T = torch.empty((H, W), dtype=torch.float32, device=dev)
+        st.n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
+    B.check(B.lib.d4dgs_render_fwd_flow(C.byref(st.splats()), C.byref(st.bins()), W, H, C.byref(_bg(bg)),
+                                        _ptr(st.img), _ptr(st.flow), _ptr(st.final_T) if keep_state else None,
+                                        _ptr(st.n_contrib) if keep_state else None, _stream()))
+    return st.img, st.flow, st
+
+
+def flow_loss(img, flow, lam, eps=1e-6, grad=True):
+    """Flow-gradient guided consistency loss (Eq. 17) of a rendered image [3,H,W] and flow
+    [2,H,W]; returns (loss as a 1-element tensor, dL/dflow or None)."""
+    img = img.contiguous().float()
+    flow = flow.contiguous().float()
+    H, W = int(img.shape[1]), int(img.shape[2])
+    nb = C.c_size_t(0)
+    B.check(B.lib.d4dgs_flow_loss_workspace_size(W, H, C.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=img.device)
+    loss = torch.empty(1, dtype=torch.float32, device=img.device)
+    dflow = torch.empty_like(flow) if grad else None
+    B.check(B.lib.d4dgs_flow_loss(_ptr(img), _ptr(flow), W, H, float(lam), float(eps), _ptr(ws), ws.numel(),
+                                  _ptr(loss), _ptr(dflow), _stream()))
+    return loss, dflow
 
 
 class _RenderFn(torch.autograd.Function):
@@ -209,6 +263,52 @@ class _RenderFn(torch.autograd.Function):
     def backward(ctx, dL_dimg):
         g = render_backward(ctx.scene, ctx.cam, ctx.t, ctx.bg, ctx.st, dL_dimg)
         return (None, None, None, None, None) + tuple(g[k] for k in FIELDS)
+
+
+class _RenderFlowFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, cam, t, bg, sh_degree, capacity, *params):
+        scene = DeviceScene(dict(zip(FIELDS, [p.detach() for p in params])), sh_degree)
+        img, flow, st = render_forward_flow(scene, cam, t, bg, capacity)
+        ctx.scene, ctx.cam, ctx.t, ctx.bg, ctx.st = scene, cam, t, bg, st
+        return img, flow
+
+    @staticmethod
+    def backward(ctx, dL_dimg, dL_dflow):
+        if dL_dimg is None:
+            dL_dimg = torch.zeros_like(ctx.st.img)
+        if dL_dflow is None:
+            dL_dflow = torch.zeros_like(ctx.st.flow)
+        g = render_backward(ctx.scene, ctx.cam, ctx.t, ctx.bg, ctx.st, dL_dimg, dL_dflow=dL_dflow)
+        return (None, None, None, None, None) + tuple(g[k] for k in FIELDS)
+
+
+class _FlowLossFn(torch.autograd.Function):
+    """Eq. 17; the gradient flows to the flow only (the image-edge weight and the
+    normalisers are constants of the loss)."""
+
+    @staticmethod
+    def forward(ctx, img, flow, lam, eps):
+        loss, dflow = flow_loss(img.detach(), flow.detach(), lam, eps, grad=True)
+        ctx.save_for_backward(dflow)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (dflow,) = ctx.saved_tensors
+        return None, dflow * g, None, None
+
+
+def render_with_flow(mean, scale, quat, opacity, t_mean, t_scale, velocity, sh, *, cam, t, sh_degree,
+                     bg=(0.0, 0.0, 0.0), capacity=None):
+    """Differentiable render of one (camera, t) view returning (image, optical flow)."""
+    return _RenderFlowFn.apply(cam, float(t), tuple(bg), int(sh_degree), capacity, mean, scale, quat, opacity,
+                               t_mean, t_scale, velocity, sh)
+
+
+def flow_gradient_loss(img, flow, lam, eps=1e-6):
+    """Differentiable flow-gradient guided consistency loss (Eq. 17)."""
+    return _FlowLossFn.apply(img, flow, float(lam), float(eps))
 
 
 def render(mean, scale, quat, opacity, t_mean, t_scale, velocity, sh, *, cam, t, sh_degree, bg=(0.0, 0.0, 0.0),
