@@ -150,9 +150,16 @@ typedef struct {
 } d4dgs_bins;
 
 /* Parameter gradients, same planar shapes as d4dgs_scene (all device, float32).
- * d4dgs_render_bwd ADDS into them; zero them first. */
+ * d4dgs_render_bwd ADDS into them; zero them first.
+ * Optional splitting statistics (Sec. 3.3, temporal splitting: time-domain splitting is
+ * guided by the gradient of the t coordinate, spatial splitting by that of xyz), all [n],
+ * NULL to skip: for every Gaussian drawn in the view (count > 0), each backward call adds
+ * |dL/dmu_t| of this view to split_grad_t, the Euclidean norm of dL/dmu (xyz) of this
+ * view to split_grad_xyz, and 1 to split_count. */
 typedef struct {
     float *mean, *scale, *quat, *opacity, *t_mean, *t_scale, *velocity, *sh;
+    float *split_grad_t, *split_grad_xyz;
+    uint32_t *split_count;
 } d4dgs_grads;
 
 int32_t d4dgs_abi_version(void);

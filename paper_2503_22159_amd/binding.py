@@ -55,7 +55,8 @@ class Bins(C.Structure):
 
 
 class Grads(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in ("mean", "scale", "quat", "opacity", "t_mean", "t_scale", "velocity", "sh")]
+    _fields_ = [(k, C.c_void_p) for k in ("mean", "scale", "quat", "opacity", "t_mean", "t_scale", "velocity", "sh",
+                                          "split_grad_t", "split_grad_xyz", "split_count")]
 
 
 class ServeConfig(C.Structure):

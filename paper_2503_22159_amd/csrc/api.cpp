@@ -265,6 +265,9 @@ d4dgs_status render_bwd_impl(const d4dgs_scene *scene, const d4dgs_camera *cam, 
     if (scene->n > 0 && (!grads->mean || !grads->scale || !grads->quat || !grads->opacity || !grads->t_mean ||
                          !grads->t_scale || !grads->velocity || !grads->sh))
         return fail(D4DGS_ERR_INVALID_ARG, "render_bwd: gradient array is NULL");
+    if ((grads->split_count != nullptr) != (grads->split_grad_t != nullptr) ||
+        (grads->split_count != nullptr) != (grads->split_grad_xyz != nullptr))
+        return fail(D4DGS_ERR_INVALID_ARG, "render_bwd: splitting statistics must be all set or all NULL");
     const SceneK sk = make_scenek(*scene);
     const CamK ck = make_camk(*cam);
     hipError_t e = launch_blend_bwd((const float4 *)splats->rec, splats->offset, bins->values, bins->ranges, ck, bg,

@@ -513,6 +513,12 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     out.opacity[gi] += g_o;
     out.t_mean[gi] += -g_tau;
     out.t_scale[gi] += g_st;
+    // splitting statistics of this view: |dL/dmu_t| and |dL/dmu|
+    if (out.split_count) {
+        out.split_grad_t[gi] += fabsf(g_tau);
+        out.split_grad_xyz[gi] += sqrtf(g_mu[0] * g_mu[0] + g_mu[1] * g_mu[1] + g_mu[2] * g_mu[2]);
+        out.split_count[gi] += 1u;
+    }
     (void)g_o;
 }
 

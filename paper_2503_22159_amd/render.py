@@ -180,8 +180,17 @@ def render_forward(scene: DeviceScene, cam, t, bg=(0.0, 0.0, 0.0), capacity=None
     return img, st
 
 
-def grads_like(scene: DeviceScene):
-    return {k: torch.zeros_like(scene.t[k]) for k in FIELDS}
+def grads_like(scene: DeviceScene, split_stats=False):
+    """Zeroed gradient arrays; with split_stats also the splitting statistics
+    (split_grad_t, split_grad_xyz float [n]; split_count int32 [n]) that every backward
+    call accumulates: |dL/dmu_t| and |dL/dmu| of the view for each drawn Gaussian."""
+    g = {k: torch.zeros_like(scene.t[k]) for k in FIELDS}
+    if split_stats:
+        dev = scene.t["mean"].device
+        g["split_grad_t"] = torch.zeros(scene.n, dtype=torch.float32, device=dev)
+        g["split_grad_xyz"] = torch.zeros(scene.n, dtype=torch.float32, device=dev)
+        g["split_count"] = torch.zeros(scene.n, dtype=torch.int32, device=dev)
+    return g
 
 
 def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, grads=None, dL_dflow=None):
@@ -195,6 +204,9 @@ def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, gra
     g = B.Grads()
     for k in FIELDS:
         setattr(g, k, grads[k].data_ptr())
+    for k in ("split_grad_t", "split_grad_xyz", "split_count"):
+        if k in grads:
+            setattr(g, k, grads[k].data_ptr())
     s = scene.struct()
     if dL_dflow is None:
         B.check(B.lib.d4dgs_render_bwd(C.byref(s), C.byref(B.camera_struct(cam)), float(t), C.byref(st.splats()),

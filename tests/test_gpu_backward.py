@@ -114,6 +114,36 @@ def test_parameter_gradients_opaque_splats(R):
     print("opaque grad rel err", errs, "masked px", nmask)
 
 
+def test_split_statistics_accumulate_per_view(R):
+    """Splitting statistics over two views: for each Gaussian drawn in a view, the view's
+    |dL/dmu_t| and |dL/dmu| are added and the view counted (GPU vs the oracle's
+    per-view parameter gradients)."""
+    import torch
+
+    sc, cam, _ = inputs.config1()
+    views = [(cam, np.float32(0.4)), (inputs.look_at((1.5, 0.5, -5.5), width=128, height=128), np.float32(0.65))]
+    ds = R.DeviceScene.from_inputs(sc)
+    grads = R.grads_like(ds, split_stats=True)
+    st_t = np.zeros(sc.n)
+    st_x = np.zeros(sc.n)
+    st_c = np.zeros(sc.n, np.int64)
+    for k, (c, t) in enumerate(views):
+        img, st = R.render_forward(ds, c, t)
+        proj, bins, res = oracle.render(sc, c, t)
+        mask = res["flags"] > 0
+        dL = inputs.upstream_grad(60 + k, c.width, c.height) * (~mask)[None]
+        R.render_backward(ds, c, t, (0.0, 0.0, 0.0), st, torch.from_numpy(dL.astype(np.float32)).cuda(), grads)
+        gp, _, _ = oracle.render_grad(sc, c, t, dL.astype(np.float64))
+        drawn = proj["count"] > 0
+        st_t[drawn] += np.abs(gp["t_mean"][drawn])
+        st_x[drawn] += np.sqrt((gp["mean"][:, drawn] ** 2).sum(axis=0))
+        st_c[drawn] += 1
+    torch.cuda.synchronize()
+    assert np.array_equal(grads["split_count"].cpu().numpy().astype(np.int64), st_c)
+    compare_group("split_grad_t", grads["split_grad_t"].cpu().numpy(), st_t)
+    compare_group("split_grad_xyz", grads["split_grad_xyz"].cpu().numpy(), st_x)
+
+
 def test_backward_is_deterministic(R):
     import torch
 
