@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-times", action="store_true", help="skip the multi-timestamp batch measurement")
     ap.add_argument("--cpu-frames", type=int, default=100)
-    ap.add_argument("--bwd-frames", type=int, default=20)
+    ap.add_argument("--bwd-frames", type=int, default=40)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB buffer three times (the reference kernel for scaling "
@@ -152,28 +152,44 @@ def sweep(args, ds, cams, times, render):
 
 def fwd_bwd(args, ds, cams, render, inputs):
     """Forward + backward at the same scene and resolution (training-style: no camera
-    cache, parameters may change between steps)."""
+    cache, every view's gradient added into one set of parameter gradients).  Views
+    alternate over two streams with their own frame buffers, so one view's forward
+    overlaps the previous view's backward; the backward passes, which all add into the
+    same gradient arrays, are kept in order by events."""
     import numpy as np
     import torch
 
     W, H = cams[0].width, cams[0].height
-    rend = render.Renderer(ds, W, H, capacity=4 * ds.n, cache=False, keep_state=True)
+    S = 2
+    rends = [render.Renderer(ds, W, H, capacity=4 * ds.n, cache=False, keep_state=True) for _ in range(S)]
+    streams = [torch.cuda.Stream() for _ in range(S)]
     grads = render.grads_like(ds)
     dL = torch.from_numpy(inputs.upstream_grad(7, W, H)).cuda()
     views = [(cams[(3 * i) % len(cams)], np.float32((i % 10) / 9.0)) for i in range(args.bwd_frames)]
-    for cam, t in views[:2]:
-        rend.render(cam, t)
-        rend.backward(cam, t, dL, grads)
+    bwd_done = [torch.cuda.Event() for _ in range(len(views) + 2)]
+
+    def run(vs):
+        prev = None
+        for i, (cam, t) in enumerate(vs):
+            r = i % S
+            with torch.cuda.stream(streams[r]):
+                rends[r].render(cam, t)
+                if prev is not None:
+                    streams[r].wait_event(prev)
+                rends[r].backward(cam, t, dL, grads)
+                ev = bwd_done[i]
+                ev.record(streams[r])
+                prev = ev
+
+    run(views[:2])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for cam, t in views:
-        rend.render(cam, t)
-        rend.backward(cam, t, dL, grads)
+    run(views)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    assert not rend.overflowed()
+    assert not any(r.overflowed() for r in rends)
     return {"frames_per_s": round(len(views) / el, 2), "ms_per_frame": round(1000 * el / len(views), 4),
-            "frames": len(views), "camera_cache": False}
+            "frames": len(views), "camera_cache": False, "streams": S}
 
 
 def times_batch(args, ds, cams, render):
