@@ -33,7 +33,6 @@ namespace d4 {
 
 namespace {
 
-constexpr int kPx = 4;
 
 __device__ __forceinline__ uint32_t inst_slot(const float4 &r2, uint32_t off, int tx, int ty) {
     const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
@@ -110,162 +109,166 @@ __device__ __forceinline__ void wave_sum9(const float v[9], float &x, float &y) 
 
 // FLOW: the flow F = sum mdot alpha T (background 0) is two more colour channels with
 // upstream gradient dLf; their colour gradients dL/dmdot go to the slot's third float4.
+//
+// One workgroup of four wavefronts per tile; wavefront w owns the 8x8 quadrant
+// (w & 1, w >> 1), one pixel per lane.  Per batch of 64 list entries (last batch first):
+// wavefront 0 stages the splats once; each wavefront culls them against its quadrant
+// and walks its kept splats from the back (a scalar bit mask), reducing its nine (or
+// eleven) per-splat sums into LDS; then 64 threads add the four quadrants' sums in a
+// fixed order, form the splat gradients and write the instance slots.  Splitting a tile
+// over four wavefronts shortens the serial chain of the longest tiles fourfold.
+constexpr int kBwdThreads = 4 * kWave;
+
 template <bool FLOW>
-__global__ __launch_bounds__(kWave) void k_blend_bwd(const float4 *__restrict__ rec,
-                                                     const uint32_t *__restrict__ offset,
-                                                     const uint32_t *__restrict__ vals,
-                                                     const uint32_t *__restrict__ ranges, CamK c, float bg0,
-                                                     float bg1, float bg2, const float *__restrict__ final_T,
-                                                     const uint32_t *__restrict__ ncontrib,
-                                                     const float *__restrict__ dL, float4 *__restrict__ ig,
-                                                     uint32_t capacity, int ntiles, int per_xcd,
-                                                     const float2 *__restrict__ mdot,
-                                                     const float *__restrict__ dLf) {
+__global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restrict__ rec,
+                                                           const uint32_t *__restrict__ offset,
+                                                           const uint32_t *__restrict__ vals,
+                                                           const uint32_t *__restrict__ ranges, CamK c, float bg0,
+                                                           float bg1, float bg2, const float *__restrict__ final_T,
+                                                           const uint32_t *__restrict__ ncontrib,
+                                                           const float *__restrict__ dL, float4 *__restrict__ ig,
+                                                           uint32_t capacity, int ntiles, int per_xcd,
+                                                           const float2 *__restrict__ mdot,
+                                                           const float *__restrict__ dLf) {
     constexpr int NR = FLOW ? 11 : 9;  // sums reduced per splat
     const int b = blockIdx.x;
     const int tile = (b & 7) * per_xcd + (b >> 3);
     if (tile >= ntiles) return;
     const int tx = tile % c.TX, ty = tile / c.TX;
-    const int ln = lane_id();
-    const int lxi = ln & 15;
+    const int tid = threadIdx.x, w = tid / kWave, ln = lane_id();
     const size_t plane = (size_t)c.W * c.H;
-    // pixel centres: (ox + 0..15, oy + 0..15)
-    const float ox = (float)(tx * kTile) + 0.5f, oy = (float)(ty * kTile) + 0.5f;
-    const float sx = ox + (float)lxi;
-    float sy[kPx], Tc[kPx], GS[kPx], g0[kPx], g1[kPx], g2[kPx], g3[kPx], g4[kPx];
-    uint32_t nc[kPx];
-    uint32_t nmax = 0;
-#pragma unroll
-    for (int k = 0; k < kPx; ++k) {
-        const int lyi = (ln >> 4) + 4 * k;
-        const int px = tx * kTile + lxi, py = ty * kTile + lyi;
-        sy[k] = oy + (float)lyi;
-        const bool in = px < c.W && py < c.H;
-        const size_t pi = (size_t)py * c.W + px;
-        Tc[k] = in ? final_T[pi] : 1.0f;
-        nc[k] = in ? ncontrib[pi] : 0u;
-        g0[k] = in ? dL[pi] : 0.0f;
-        g1[k] = in ? dL[plane + pi] : 0.0f;
-        g2[k] = in ? dL[2 * plane + pi] : 0.0f;
-        g3[k] = FLOW && in ? dLf[pi] : 0.0f;
-        g4[k] = FLOW && in ? dLf[plane + pi] : 0.0f;
-        GS[k] = Tc[k] * (g0[k] * bg0 + g1[k] * bg1 + g2[k] * bg2);
-        nmax = max(nmax, nc[k]);
-    }
-    nmax = __builtin_amdgcn_readfirstlane(wave_max_u32(nmax));
+    // this wavefront's 8x8 quadrant and this lane's pixel
+    const int qx0 = tx * kTile + (w & 1) * 8, qy0 = ty * kTile + (w >> 1) * 8;
+    const int px = qx0 + (ln & 7), py = qy0 + (ln >> 3);
+    const float sx = (float)px + 0.5f, sy = (float)py + 0.5f;
+    const float wx0 = (float)qx0 + 0.5f, wx1 = wx0 + 7.0f, wy0 = (float)qy0 + 0.5f, wy1 = wy0 + 7.0f;
+    const bool in = px < c.W && py < c.H;
+    const size_t pi = (size_t)py * c.W + px;
+    float Tc = in ? final_T[pi] : 1.0f;
+    const uint32_t nc = in ? ncontrib[pi] : 0u;
+    const float g0 = in ? dL[pi] : 0.0f, g1 = in ? dL[plane + pi] : 0.0f, g2 = in ? dL[2 * plane + pi] : 0.0f;
+    const float g3 = FLOW && in ? dLf[pi] : 0.0f, g4 = FLOW && in ? dLf[plane + pi] : 0.0f;
+    float GS = Tc * (g0 * bg0 + g1 * bg1 + g2 * bg2);  // g . S with S = T_final bg
+    // tile-wide last contributor
+    __shared__ uint32_t wmax[4];
+    const uint32_t wm = __builtin_amdgcn_readfirstlane(wave_max_u32(nc));
+    if (ln == 0) wmax[w] = wm;
+    __syncthreads();
+    const uint32_t nmax = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     // instances behind every pixel's last contributor get zero gradients
-    for (uint32_t j = start + nmax + ln; j < end; j += kWave) {
+    for (uint32_t j = start + nmax + tid; j < end; j += kBwdThreads) {
         const uint32_t gi = vals[j];
         const uint32_t slot = inst_slot(rec[3 * (size_t)gi + 2], offset[gi], tx, ty);
         if (slot < capacity) zero_slot(ig, slot);  // false only after an instance overflow
     }
-    // s2 = {b, bits(plain << 31 | list position), bits(slot), amax}, s3 = {conic a, b, c, -}
+    // staged batch: s2 = {b, bits(plain << 31 | list position), extent x, extent y},
+    // s3 = {conic a, b, c, amax}
     __shared__ float4 s0[kWave], s1[kWave], s2[kWave], s3[kWave];
+    __shared__ uint32_t sslot[kWave];
     __shared__ float2 s4[FLOW ? kWave : 1];  // mdot
-    __shared__ float red[kWave * NR];
-    const float wx1 = ox + (float)(kTile - 1), wy1 = oy + (float)(kTile - 1);
-    // batches of 64 list entries, last batch first
+    __shared__ uint64_t kmask[4];
+    __shared__ float red[4 * kWave * NR];
     for (uint32_t jb = start + nmax; jb > start;) {
         const uint32_t j0 = jb - start > (uint32_t)kWave ? jb - kWave : start;
-        const uint32_t j = j0 + ln;
-        bool keep = false, plain = false;
-        float4 f0, f1, f2, r0, r1;
-        float2 fm = make_float2(0.f, 0.f);
-        uint32_t slot = 0;
-        if (j < jb) {
+        const uint32_t nb = jb - j0;
+        if (w == 0 && (uint32_t)ln < nb) {
+            const uint32_t j = j0 + ln;
             const uint32_t gi = vals[j];
-            r0 = rec[3 * (size_t)gi + 0];
-            r1 = rec[3 * (size_t)gi + 1];
-            const float4 r2 = rec[3 * (size_t)gi + 2];
+            const float4 r0 = rec[3 * (size_t)gi + 0], r1 = rec[3 * (size_t)gi + 1], r2 = rec[3 * (size_t)gi + 2];
+            float4 f0, f1, f2;
             fold_raw(r0, r1, r2, f0, f1, f2);
-            slot = inst_slot(r2, offset[gi], tx, ty);
-            if (FLOW) fm = mdot[gi];
-            keep = !splat_misses(f0, f2, ox, wx1, oy, wy1);
-            plain = splat_plain(r0, r1);
-            if (!keep && slot < capacity) zero_slot(ig, slot);  // no pixel of the tile reaches 1/255
-        }
-        const uint64_t km = __ballot(keep);
-        if (keep) {
-            const int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-            s0[pos] = f0;
-            s1[pos] = f1;
-            s2[pos] = make_float4(f2.x, __uint_as_float((plain ? 0x80000000u : 0u) | (j - start)),
-                                  __uint_as_float(slot), r1.y);
-            s3[pos] = make_float4(r0.z, r0.w, r1.x, 0.0f);
-            if (FLOW) s4[pos] = fm;
+            s0[ln] = f0;
+            s1[ln] = f1;
+            s2[ln] = make_float4(f2.x, __uint_as_float((splat_plain(r0, r1) ? 0x80000000u : 0u) | (j - start)), f2.z,
+                                 f2.w);
+            s3[ln] = make_float4(r0.z, r0.w, r1.x, r1.y);
+            sslot[ln] = inst_slot(r2, offset[gi], tx, ty);
+            if (FLOW) s4[ln] = mdot[gi];
         }
         __syncthreads();
-        const int nb = __popcll(km);
-        for (int i = nb - 1; i >= 0; --i) {
+        // this quadrant's splats: lane i tests staged splat i
+        bool keep = false;
+        if ((uint32_t)ln < nb) {
+            const float4 h0 = s0[ln], h2 = s2[ln];
+            keep = !splat_misses(h0, make_float4(0.f, 0.f, h2.z, h2.w), wx0, wx1, wy0, wy1);
+        }
+        uint64_t km = __ballot(keep);
+        if (ln == 0) kmask[w] = km;
+        while (km) {
+            const int i = 63 - __builtin_clzll(km);  // from the back of the list
+            km &= ~(1ull << i);
             const float4 h0 = s0[i], h1 = s1[i];
             const float2 h2 = *reinterpret_cast<const float2 *>(&s2[i]);
             const uint32_t tag = __builtin_amdgcn_readfirstlane(__float_as_uint(h2.y));
             const uint32_t jj = tag & 0x7fffffffu;  // position in the tile's list
             // the forward's per-splat tests: no "exponent > 0" skip for plain splats
             const uint64_t pos_ok = (tag >> 31) ? ~0ull : 0ull;
-            const float dx = sx - h0.x;
+            const float dx = sx - h0.x, dy = sy - h0.y;
             const ColTerms ct = col_terms(h0, h1, dx);
-            float d0 = 0.f, e1 = 0.f, e2 = 0.f, ar = 0.f, ag = 0.f, ab = 0.f, af0 = 0.f, af1 = 0.f;
-            const float2 h4 = FLOW ? s4[i] : make_float2(0.f, 0.f);
-#pragma unroll
-            for (int k = 0; k < kPx; ++k) {
-                const float dy = sy[k] - h0.y;
-                const float q = pix_exponent(ct, h1, dy);
-                const float e = exp2_fast(q);
-                const float alpha = fminf(kAlphaMax, e);
-                const uint64_t ok =
-                    __ballot(jj < nc[k]) & (pos_ok | __ballot(!(q > h1.y))) & __ballot(alpha >= kAlphaMin);
-                const bool okb = __builtin_amdgcn_inverse_ballot_w64(ok);
-                const bool unclamped = __builtin_amdgcn_inverse_ballot_w64(ok & __ballot(e <= kAlphaMax));
-                const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-                const float Ti = Tc[k] * inv;  // transmittance in front of this splat
-                float gc = __builtin_fmaf(g2[k], h2.x, __builtin_fmaf(g1[k], h1.w, g0[k] * h1.z));
-                if (FLOW) gc = __builtin_fmaf(g4[k], h4.y, __builtin_fmaf(g3[k], h4.x, gc));
-                const float wgt = okb ? alpha * Ti : 0.0f;
-                const float da = __builtin_fmaf(-inv, GS[k], Ti * gc);
-                GS[k] = __builtin_fmaf(gc, wgt, GS[k]);
-                ar = __builtin_fmaf(g0[k], wgt, ar);
-                ag = __builtin_fmaf(g1[k], wgt, ag);
-                ab = __builtin_fmaf(g2[k], wgt, ab);
-                if (FLOW) {
-                    af0 = __builtin_fmaf(g3[k], wgt, af0);
-                    af1 = __builtin_fmaf(g4[k], wgt, af1);
-                }
-                Tc[k] = okb ? Ti : Tc[k];
-                // d/d(power); zero where alpha is clamped (alpha = amax exp(power) otherwise)
-                const float dp = unclamped ? da * alpha : 0.0f;
-                const float dpdy = dp * dy;
-                d0 += dp;
-                e1 += dpdy;
-                e2 = __builtin_fmaf(dpdy, dy, e2);
+            const float q = pix_exponent(ct, h1, dy);
+            const float e = exp2_fast(q);
+            const float alpha = fminf(kAlphaMax, e);
+            const uint64_t ok = __ballot(jj < nc) & (pos_ok | __ballot(!(q > h1.y))) & __ballot(alpha >= kAlphaMin);
+            const bool okb = __builtin_amdgcn_inverse_ballot_w64(ok);
+            const bool unclamped = __builtin_amdgcn_inverse_ballot_w64(ok & __ballot(e <= kAlphaMax));
+            const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+            const float Ti = Tc * inv;  // transmittance in front of this splat
+            float gc = __builtin_fmaf(g2, h2.x, __builtin_fmaf(g1, h1.w, g0 * h1.z));
+            float2 h4 = make_float2(0.f, 0.f);
+            if (FLOW) {
+                h4 = s4[i];
+                gc = __builtin_fmaf(g4, h4.y, __builtin_fmaf(g3, h4.x, gc));
             }
-            const float v[9] = {d0, dx * d0, e1, (dx * dx) * d0, dx * e1, e2, ar, ag, ab};
+            const float wgt = okb ? alpha * Ti : 0.0f;
+            const float da = __builtin_fmaf(-inv, GS, Ti * gc);
+            GS = __builtin_fmaf(gc, wgt, GS);
+            Tc = okb ? Ti : Tc;
+            // d/d(power); zero where alpha is clamped (alpha = amax exp(power) otherwise)
+            const float dp = unclamped ? da * alpha : 0.0f;
+            const float dpx = dp * dx, dpy = dp * dy;
+            const float v[9] = {dp, dpx, dpy, dpx * dx, dpx * dy, dpy * dy, g0 * wgt, g1 * wgt, g2 * wgt};
             float x, y;
             wave_sum9(v, x, y);
-            if (ln < 9) red[NR * i + (ln < 8 ? red_index(ln) : 8)] = ln < 8 ? x : y;
+            float* rw = &red[(w * kWave + i) * NR];
+            if (ln < 9) rw[ln < 8 ? red_index(ln) : 8] = ln < 8 ? x : y;
             if (FLOW) {
-                const float f0 = wave_allsum(af0), f1 = wave_allsum(af1);
+                const float f0 = wave_allsum(g3 * wgt), f1 = wave_allsum(g4 * wgt);
                 if (ln == 0) {
-                    red[NR * i + 9] = f0;
-                    red[NR * i + 10] = f1;
+                    rw[9] = f0;
+                    rw[10] = f1;
                 }
             }
         }
         __syncthreads();
-        // one lane per kept splat: moments -> gradients of the 2D mean (d power / d m =
-        // Q d), the conic (-d d^T / 2, off-diagonal -dx dy) and amax (alpha / amax per
-        // unclamped pixel)
-        if (ln < nb) {
-            const float *m = &red[NR * ln];
-            const float P0 = m[0], Sx = m[1], Sy = m[2], Sxx = m[3], Sxy = m[4], Syy = m[5];
-            const float4 h2 = s2[ln], h3 = s3[ln];
-            const uint32_t sl = __float_as_uint(h2.z);
-            if (sl < capacity) {
-                ig[3 * (size_t)sl + 0] = make_float4(h3.x * Sx + h3.y * Sy, h3.z * Sy + h3.y * Sx, -0.5f * Sxx, -Sxy);
-                ig[3 * (size_t)sl + 1] = make_float4(-0.5f * Syy, P0 / h2.w, m[6], m[7]);
-                ig[3 * (size_t)sl + 2] = make_float4(m[8], FLOW ? m[9] : 0.f, FLOW ? m[10] : 0.f, 0.f);
+        // one thread per staged splat: add the quadrants' sums (fixed order), turn the
+        // moments into the gradients of the 2D mean (d power / d m = Q d), the conic
+        // (-d d^T / 2, off-diagonal -dx dy) and amax (alpha / amax where unclamped)
+        if (tid < (int)nb) {
+            const uint32_t sl = sslot[tid];
+            float m[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) m[k] = 0.0f;
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (!((kmask[q] >> tid) & 1ull)) continue;
+                any = true;
+                const float *rq = &red[(q * kWave + tid) * NR];
+#pragma unroll
+                for (int k = 0; k < NR; ++k) m[k] += rq[k];
+            }
+            if (sl < capacity) {  // false only after an instance overflow
+                if (!any) {
+                    zero_slot(ig, sl);  // no pixel of the tile reaches 1/255
+                } else {
+                    const float4 h3 = s3[tid];
+                    const float P0 = m[0], Sx = m[1], Sy = m[2], Sxx = m[3], Sxy = m[4], Syy = m[5];
+                    ig[3 * (size_t)sl + 0] =
+                        make_float4(h3.x * Sx + h3.y * Sy, h3.z * Sy + h3.y * Sx, -0.5f * Sxx, -Sxy);
+                    ig[3 * (size_t)sl + 1] = make_float4(-0.5f * Syy, P0 / h3.w, m[6], m[7]);
+                    ig[3 * (size_t)sl + 2] = make_float4(m[8], FLOW ? m[9] : 0.f, FLOW ? m[10] : 0.f, 0.f);
+                }
             }
         }
         __syncthreads();
@@ -532,11 +535,11 @@ hipError_t launch_blend_bwd(const float4 *rec, const uint32_t *offset, const uin
     if (ntiles == 0) return hipSuccess;
     const int per_xcd = (ntiles + 7) / 8;
     if (mdot && dL_dflow)
-        hipLaunchKernelGGL(k_blend_bwd<true>, dim3(per_xcd * 8), dim3(kWave), 0, st, rec, offset, vals, ranges, c,
+        hipLaunchKernelGGL(k_blend_bwd<true>, dim3(per_xcd * 8), dim3(kBwdThreads), 0, st, rec, offset, vals, ranges, c,
                            bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, ntiles,
                            per_xcd, mdot, dL_dflow);
     else
-        hipLaunchKernelGGL(k_blend_bwd<false>, dim3(per_xcd * 8), dim3(kWave), 0, st, rec, offset, vals, ranges, c,
+        hipLaunchKernelGGL(k_blend_bwd<false>, dim3(per_xcd * 8), dim3(kBwdThreads), 0, st, rec, offset, vals, ranges, c,
                            bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, ntiles,
                            per_xcd, nullptr, nullptr);
     return hipGetLastError();
