@@ -324,11 +324,27 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
                                                         const float4 *__restrict__ ig, uint32_t capacity,
                                                         d4dgs_grads out) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    const int gi = blockIdx.x * kBlock + threadIdx.x;
     const int n = s.n;
-    if (gi >= n) return;
+    // the block's drawn Gaussians (count > 0), compacted in LDS so that the busy
+    // wavefronts are full: about half of the Gaussians are culled at any t
+    __shared__ uint32_t list[kBlock];
+    __shared__ uint32_t wcnt[kBlock / kWave];
+    {
+        const int g0 = blockIdx.x * kBlock + threadIdx.x;
+        const bool drawn = g0 < n && count[g0] > 0;
+        const uint64_t bal = __ballot(drawn);
+        const uint32_t rank = __popcll(bal & lanemask_lt());
+        if (lane_id() == 0) wcnt[threadIdx.x / kWave] = __popcll(bal);
+        __syncthreads();
+        uint32_t base = 0;
+        for (int i = 0; i < (int)threadIdx.x / kWave; ++i) base += wcnt[i];
+        if (drawn) list[base + rank] = (uint32_t)g0;
+        __syncthreads();
+    }
+    const uint32_t ndrawn = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (threadIdx.x >= ndrawn) return;
+    const int gi = (int)list[threadIdx.x];
     const uint32_t cnt = count[gi];
-    if (cnt == 0) return;
     if ((uint64_t)offset[gi] + cnt > capacity) return;  // instances lost to an overflow
     // 1. sum this Gaussian's instance gradients in emission order
     float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gam = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
@@ -482,7 +498,11 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     const float dotq = qw * gqw + qx * gqx + qy * gqy + qz * gqz;
     const float g_q[4] = {(gqw - qw * dotq) / nrm, (gqx - qx * dotq) / nrm, (gqy - qy * dotq) / nrm,
                           (gqz - qz * dotq) / nrm};
-    // colour: rgb = max(0, sum_k Y_k(d) sh_k + 0.5), d = (mu - campos) / |mu - campos|
+    // colour: rgb = max(0, sum_k Y_k(d) sh_k + 0.5), d = (mu - campos) / |mu - campos|.
+    // The gradient arrays are only written here and never alias the scene, so each group
+    // of old values is loaded together before the stores (no serialised round trips).
+    const float *__restrict__ shp = s.sh;
+    float *__restrict__ osh = out.sh;
     {
         const float dx0 = mu[0] - c.campos[0], dy0 = mu[1] - c.campos[1], dz0 = mu[2] - c.campos[2];
         const float len = sqrtf(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
@@ -491,14 +511,21 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
         sh_basis_grad<DEG>(d[0], d[1], d[2], Y, dY);
         const float grgb[3] = {gr, gg, gb};
         float g_d[3] = {0.f, 0.f, 0.f};
+#pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
+            float shv[K], old[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) shv[k] = shp[(size_t)(k * 3 + ch) * n + gi];
             float raw = 0.5f;
-            for (int k = 0; k < K; ++k) raw += Y[k] * s.sh[(size_t)(k * 3 + ch) * n + gi];
-            if (raw < 0.f) continue;
+#pragma unroll
+            for (int k = 0; k < K; ++k) raw += Y[k] * shv[k];
+            if (raw < 0.f) continue;  // clamped at 0: no gradient
+#pragma unroll
+            for (int k = 0; k < K; ++k) old[k] = osh[(size_t)(k * 3 + ch) * n + gi];
+#pragma unroll
             for (int k = 0; k < K; ++k) {
-                const size_t idx = (size_t)(k * 3 + ch) * n + gi;
-                out.sh[idx] += Y[k] * grgb[ch];
-                const float f = s.sh[idx] * grgb[ch];
+                osh[(size_t)(k * 3 + ch) * n + gi] = old[k] + Y[k] * grgb[ch];
+                const float f = shv[k] * grgb[ch];
                 g_d[0] += f * dY[k][0];
                 g_d[1] += f * dY[k][1];
                 g_d[2] += f * dY[k][2];
@@ -507,20 +534,44 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
         const float dd = d[0] * g_d[0] + d[1] * g_d[1] + d[2] * g_d[2];
         for (int i = 0; i < 3; ++i) g_mu[i] += (g_d[i] - d[i] * dd) / len;
     }
+    float *__restrict__ omean = out.mean;
+    float *__restrict__ oscale = out.scale;
+    float *__restrict__ ovel = out.velocity;
+    float *__restrict__ oquat = out.quat;
+    float *__restrict__ oop = out.opacity;
+    float *__restrict__ omut = out.t_mean;
+    float *__restrict__ ost = out.t_scale;
+    float om[3], os[3], ov[3], oq[4];
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
-        out.mean[i * n + gi] += g_mu[i];
-        out.scale[i * n + gi] += g_s[i];
-        out.velocity[i * n + gi] += g_v[i];
+        om[i] = omean[i * n + gi];
+        os[i] = oscale[i * n + gi];
+        ov[i] = ovel[i * n + gi];
     }
-    for (int i = 0; i < 4; ++i) out.quat[i * n + gi] += g_q[i];
-    out.opacity[gi] += g_o;
-    out.t_mean[gi] += -g_tau;
-    out.t_scale[gi] += g_st;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) oq[i] = oquat[i * n + gi];
+    const float oo = oop[gi], ot = omut[gi], o_s = ost[gi];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        omean[i * n + gi] = om[i] + g_mu[i];
+        oscale[i * n + gi] = os[i] + g_s[i];
+        ovel[i * n + gi] = ov[i] + g_v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) oquat[i * n + gi] = oq[i] + g_q[i];
+    oop[gi] = oo + g_o;
+    omut[gi] = ot - g_tau;
+    ost[gi] = o_s + g_st;
     // splitting statistics of this view: |dL/dmu_t| and |dL/dmu|
     if (out.split_count) {
-        out.split_grad_t[gi] += fabsf(g_tau);
-        out.split_grad_xyz[gi] += sqrtf(g_mu[0] * g_mu[0] + g_mu[1] * g_mu[1] + g_mu[2] * g_mu[2]);
-        out.split_count[gi] += 1u;
+        float *__restrict__ sgt = out.split_grad_t;
+        float *__restrict__ sgx = out.split_grad_xyz;
+        uint32_t *__restrict__ scn = out.split_count;
+        const float a = sgt[gi], bx = sgx[gi];
+        const uint32_t cn = scn[gi];
+        sgt[gi] = a + fabsf(g_tau);
+        sgx[gi] = bx + sqrtf(g_mu[0] * g_mu[0] + g_mu[1] * g_mu[1] + g_mu[2] * g_mu[2]);
+        scn[gi] = cn + 1u;
     }
     (void)g_o;
 }
