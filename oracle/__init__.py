@@ -76,7 +76,7 @@ def lib():
         L.oc_version.restype = C.c_int
         for suf in ("f32", "f64"):
             f = getattr(L, "oc_project_" + suf)
-            f.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 13
+            f.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 14
             f.restype = None
         L.oc_bin.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, P]
         L.oc_bin.restype = C.c_int64
@@ -96,11 +96,36 @@ def lib():
         L.oc_project_bwd_flow.restype = None
         L.oc_sh_basis.argtypes = [C.c_int, C.c_int, P, P]
         L.oc_sh_basis.restype = None
+        L.oc_set_motion.argtypes = [C.c_int]
+        L.oc_set_motion.restype = None
+        L.oc_get_motion.restype = C.c_int
         L.oc_set_threads.argtypes = [C.c_int]
         L.oc_set_threads.restype = None
         L.oc_num_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+MOTION_LINEAR, MOTION_EXACT, MOTION_FROZEN_J = 0, 1, 2
+
+
+class motion:
+    """Context manager selecting the time stage's motion / covariance model (the readings
+    of Eq. 13-14): MOTION_LINEAR (default: the 2D mean moves linearly, Eq. 13 as printed,
+    Jacobian at the moved mean), MOTION_EXACT (the 2D mean is the exact projection of
+    the moved mean), MOTION_FROZEN_J (linear motion, Jacobian at the camera stage's
+    mean)."""
+
+    def __init__(self, mode):
+        self.mode = int(mode)
+
+    def __enter__(self):
+        self.prev = lib().oc_get_motion()
+        lib().oc_set_motion(self.mode)
+        return self
+
+    def __exit__(self, *exc):
+        lib().oc_set_motion(self.prev)
 
 
 def set_threads(n):
@@ -156,7 +181,8 @@ def project(scene, cam, t, prec="f32", arrays=None):
     c = _cam_struct(cam)
     dt = np.float32 if prec == "f32" else np.float64
     out = {k: np.zeros((d, n), dt) for k, d in
-           (("p", 3), ("u", 3), ("covc", 6), ("m0", 2), ("md", 2), ("rgb", 3), ("m", 2), ("conic", 3))}
+           (("p", 3), ("u", 3), ("covc", 6), ("m0", 2), ("md", 2), ("rgb", 3), ("m", 2), ("conic", 3),
+            ("mdt", 2))}
     out["amax"] = np.zeros(n, dt)
     out["w"] = np.zeros(n, dt)
     out["depth"] = np.zeros(n, np.float32)
@@ -164,7 +190,7 @@ def project(scene, cam, t, prec="f32", arrays=None):
     out["count"] = np.zeros(n, np.int32)
     f = getattr(lib(), "oc_project_" + prec)
     f(C.byref(s), C.byref(c), float(t), *[_p(out[k]) for k in
-      ("p", "u", "covc", "m0", "md", "rgb", "m", "conic", "amax", "w", "depth", "rect", "count")])
+      ("p", "u", "covc", "m0", "md", "rgb", "m", "conic", "amax", "w", "depth", "rect", "count", "mdt")])
     del keep
     out["n"] = n
     return out
@@ -204,7 +230,7 @@ def blend(proj, bins, cam, bg=(0.0, 0.0, 0.0), flow=False):
     if flow:
         fo = np.zeros((2, H, W))
         ne = lib().oc_blend_flow(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])), _p(_f64(proj["amax"])),
-                                 _p(_f64(proj["rgb"])), _p(_f64(proj["md"])), _p(np.ascontiguousarray(vals)),
+                                 _p(_f64(proj["rgb"])), _p(_f64(proj["mdt"])), _p(np.ascontiguousarray(vals)),
                                  _p(np.ascontiguousarray(bins["ranges"], np.uint32)), _p(bgv), _p(img), _p(fo),
                                  _p(T), _p(nc), _p(fl))
         return {"img": img, "flow": fo, "final_T": T, "n_contrib": nc, "flags": fl, "n_eval": int(ne)}
@@ -232,18 +258,19 @@ def blend_bruteforce(proj, cam, bg=(0.0, 0.0, 0.0)):
 
 def blend_bwd(proj, bins, cam, dL_dimg, bg=(0.0, 0.0, 0.0), dL_dflow=None):
     """Adjoint of blend: splat-level gradients of sum(dL_dimg * img) (+ sum(dL_dflow *
-    flow) when dL_dflow is given, then also g["md"])."""
+    flow) when dL_dflow is given, then also g["mdt"], the gradient of the splats' flow
+    velocities)."""
     n, W, H = proj["n"], cam.width, cam.height
     g = {"m": np.zeros((2, n)), "conic": np.zeros((3, n)), "amax": np.zeros(n), "rgb": np.zeros((3, n))}
     err = np.zeros(1)
     vals = bins["values"] if bins["I"] > 0 else np.zeros(1, np.uint32)
     if dL_dflow is not None:
-        g["md"] = np.zeros((2, n))
+        g["mdt"] = np.zeros((2, n))
         lib().oc_blend_bwd_flow(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])), _p(_f64(proj["amax"])),
-                                _p(_f64(proj["rgb"])), _p(_f64(proj["md"])), _p(np.ascontiguousarray(vals)),
+                                _p(_f64(proj["rgb"])), _p(_f64(proj["mdt"])), _p(np.ascontiguousarray(vals)),
                                 _p(np.ascontiguousarray(bins["ranges"], np.uint32)), _p(_f64(bg)),
                                 _p(_f64(dL_dimg)), _p(_f64(dL_dflow)), _p(g["m"]), _p(g["conic"]),
-                                _p(g["amax"]), _p(g["rgb"]), _p(g["md"]), _p(err))
+                                _p(g["amax"]), _p(g["rgb"]), _p(g["mdt"]), _p(err))
     else:
         lib().oc_blend_bwd(n, W, H, _p(_f64(proj["m"])), _p(_f64(proj["conic"])), _p(_f64(proj["amax"])),
                            _p(_f64(proj["rgb"])), _p(np.ascontiguousarray(vals)),
@@ -263,7 +290,7 @@ def project_bwd(scene, cam, t, active, gsplat, arrays=None):
     s, keep = _scene_struct(arr, n, deg)
     c = _cam_struct(cam)
     out = np.zeros((P, n))
-    gmd = gsplat.get("md")
+    gmd = gsplat.get("mdt")
     lib().oc_project_bwd_flow(C.byref(s), C.byref(c), float(t), _p(np.ascontiguousarray(active, np.int32)),
                               _p(_f64(gsplat["m"])), _p(_f64(gsplat["conic"])), _p(_f64(gsplat["amax"])),
                               _p(_f64(gsplat["rgb"])), _p(_f64(gmd)) if gmd is not None else None, _p(out))

@@ -43,6 +43,17 @@
 #define OC_FLAG_T_REL 5e-4
 #define OC_FLAG_POWER_REL 1e-5
 
+/* Motion / covariance model of the time stage (the readings of Eq. 13-14 made
+ * switchable): 0 = the 2D mean moves linearly (Eq. 13 as printed), Jacobian at the
+ * moved mean; 1 = the 2D mean is the exact projection of the moved mean; 2 = linear
+ * motion, Jacobian frozen at the camera stage's mean (fully deferred covariance). */
+#define OC_MOTION_LINEAR 0
+#define OC_MOTION_EXACT 1
+#define OC_MOTION_FROZEN_J 2
+static int oc_motion = OC_MOTION_LINEAR;
+void oc_set_motion(int m) { oc_motion = m; }
+int oc_get_motion(void) { return oc_motion; }
+
 typedef struct {
     int32_t n, sh_degree;
     const double *mean;     /* [3][n] */
@@ -195,11 +206,12 @@ int oc_version(void) { return OC_VERSION; }
 /* ---------------- projection (camera stage + time stage) ----------------
  * Outputs are planar: p[3n], u[3n], covc[6n], m0[2n], md[2n], rgb[3n], m[2n],
  * conic[3n], amax[n], w[n], depth[n] (FP32 bits of the camera-space z at t),
- * rect[4n] (x0,y0,x1,y1), count[n].  Any output pointer may be NULL.        */
+ * rect[4n] (x0,y0,x1,y1), count[n], mdt[2n] (the 2D mean's velocity at t, the flow).
+ * Any output pointer may be NULL.                                             */
 #define DEFINE_PROJECT(SUF, T)                                                                       \
     void oc_project_##SUF(const oc_scene *s, const oc_camera *cam, double t, T *p, T *u, T *covc,   \
                           T *m0, T *md, T *rgb, T *m, T *conic, T *amax, T *w, float *depth,         \
-                          int32_t *rect, int32_t *count)                                             \
+                          int32_t *rect, int32_t *count, T *mdt)                                     \
     {                                                                                                \
         int n = s->n, P = n_params(s->sh_degree);                                                    \
         _Pragma("omp parallel for schedule(static)") for (int g = 0; g < n; ++g)                     \
@@ -222,6 +234,7 @@ int oc_version(void) { return OC_VERSION; }
                 if (m0) m0[i * n + g] = r.m0[i];                                                     \
                 if (md) md[i * n + g] = r.md[i];                                                     \
                 if (m) m[i * n + g] = r.m[i];                                                        \
+                if (mdt) mdt[i * n + g] = r.mdt[i];                                                  \
             }                                                                                        \
             if (amax) amax[g] = r.amax;                                                              \
             if (w) w[g] = r.w;                                                                       \
@@ -550,7 +563,7 @@ void oc_project_bwd_flow(const oc_scene *s, const oc_camera *cam, double t, cons
             for (int i = 0; i < 3; ++i) d += g_conic[i * n + g] * cimag(r.conic[i]) / h;
             d += g_amax[g] * cimag(r.amax) / h;
             for (int c = 0; c < 3; ++c) d += g_rgb[c * n + g] * cimag(r.rgb[c]) / h;
-            if (g_md) d += g_md[g] * cimag(r.md[0]) / h + g_md[n + g] * cimag(r.md[1]) / h;
+            if (g_md) d += g_md[g] * cimag(r.mdt[0]) / h + g_md[n + g] * cimag(r.mdt[1]) / h;
             g_prm[(size_t)j * n + g] = d;
         }
     }

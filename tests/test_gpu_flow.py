@@ -46,9 +46,9 @@ def test_flow_render_matches_oracle(R, case):
     compare_images(img.cpu().numpy(), st.final_T.cpu().numpy(), st.n_contrib.cpu().numpy().view(np.uint32), res)
     act = proj["count"] > 0
     md_gpu = st.mdot.view(-1, 2).cpu().numpy().T
-    np.testing.assert_allclose(md_gpu[:, act], proj["md"][:, act], rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(md_gpu[:, act], proj["mdt"][:, act], rtol=1e-6, atol=1e-6)
     flagged = (res["flags"] & 7) > 0
-    scale = max(1.0, float(np.abs(proj["md"][:, act]).max()))
+    scale = max(1.0, float(np.abs(proj["mdt"][:, act]).max()))
     d = np.abs(flow.cpu().numpy().astype(np.float64) - res["flow"]).max(axis=0)
     assert d[~flagged].max() <= 1e-4 * scale, (d[~flagged].max(), scale)
 
@@ -124,7 +124,7 @@ def test_flow_backward_matches_oracle(R):
     sums = np.zeros((n, 12))
     for gi in np.nonzero(cnt)[0]:
         sums[gi] = ig[off[gi]:off[gi] + cnt[gi]].sum(axis=0)
-    compare_group("md", sums[:, 9:11].T, gs_o["md"])
+    compare_group("mdt", sums[:, 9:11].T, gs_o["mdt"])
 
 
 def test_autograd_flow_loss_chain(R):

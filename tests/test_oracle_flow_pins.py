@@ -194,7 +194,7 @@ def test_projection_adjoint_of_md_matches_fd(oracle_lib):
     rng = np.random.default_rng(5)
     z = lambda *shp: np.zeros(shp)
     gsplat = {"m": z(2, sc.n), "conic": z(3, sc.n), "amax": z(sc.n), "rgb": z(3, sc.n),
-              "md": rng.normal(size=(2, sc.n))}
+              "mdt": rng.normal(size=(2, sc.n))}
     active = (proj["count"] > 0).astype(np.int32)
     gp = oracle_lib.project_bwd(sc, cam, t, active, gsplat, base)
     act = active.astype(bool)
@@ -205,6 +205,6 @@ def test_projection_adjoint_of_md_matches_fd(oracle_lib):
             am = {k: v.copy() for k, v in base.items()}
             ap[name][idx] += h
             am[name][idx] -= h
-            fd = ((gsplat["md"] * oracle_lib.project(sc, cam, t, "f64", ap)["md"]).sum(axis=0) -
-                  (gsplat["md"] * oracle_lib.project(sc, cam, t, "f64", am)["md"]).sum(axis=0)) / (2 * h)
+            fd = ((gsplat["mdt"] * oracle_lib.project(sc, cam, t, "f64", ap)["mdt"]).sum(axis=0) -
+                  (gsplat["mdt"] * oracle_lib.project(sc, cam, t, "f64", am)["mdt"]).sum(axis=0)) / (2 * h)
             np.testing.assert_allclose(gp[name][idx][act], fd[act], rtol=1e-6, atol=1e-9 * np.abs(fd).max())
