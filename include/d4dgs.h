@@ -124,9 +124,18 @@ typedef struct {
  *   offset [n] uint32 exclusive prefix of count (written by d4dgs_bin_sort).
  *   partial [ceil(capacity / 256)] uint32 scratch: per-block sums of count written by
  *          d4dgs_project and turned into block offsets by d4dgs_bin_sort.
- *   mdot   [n][2] floats, optional (NULL: not written): the screen-space velocity of
- *          the 2D mean, dm/dt = f u_xy / p_z in pixels per unit of t (Eq. 13), for
- *          Gaussians with count > 0.  Needed by the flow render and its adjoint. */
+ *   mdot   [n][2] floats, optional (NULL: not written): the velocity of the 2D mean at
+ *          t in pixels per unit of t -- f u_xy / p_z under the linear motion of Eq. 13 --
+ *          for Gaussians with count > 0.  Needed by the flow render and its adjoint.
+ *   motion the time stage's motion / covariance model (d4dgs_motion), chosen by the
+ *          caller: d4dgs_project computes with it and the adjoints differentiate it. */
+typedef enum {
+    D4DGS_MOTION_LINEAR = 0,   /* Eq. 13 as printed: m = m0 + tau mdot; Jacobian at the moved mean */
+    D4DGS_MOTION_EXACT = 1,    /* m = projection of the moved camera-space mean p + tau u */
+    D4DGS_MOTION_FROZEN_J = 2  /* linear motion; Jacobian at the camera stage's mean p, so the
+                                  2D covariance does not change with t */
+} d4dgs_motion;
+
 typedef struct {
     int32_t capacity;
     float *rec;
@@ -134,6 +143,7 @@ typedef struct {
     uint32_t *offset;
     uint32_t *partial;
     float *mdot;
+    int32_t motion;
 } d4dgs_splats;
 
 /* Sorted tile lists written by d4dgs_bin_sort (all device, caller-owned).

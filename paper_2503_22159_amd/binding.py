@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libd4dgs.so")
 
 ABI_VERSION = 2
+MOTION_LINEAR, MOTION_EXACT, MOTION_FROZEN_J = 0, 1, 2  # d4dgs_motion
 TILE = 16
 CAM_REC_FLOATS = 19
 REC_FLOATS = 12
@@ -46,7 +47,7 @@ class CamCache(C.Structure):
 
 class Splats(C.Structure):
     _fields_ = [("capacity", C.c_int32), ("rec", C.c_void_p), ("count", C.c_void_p), ("offset", C.c_void_p),
-                ("partial", C.c_void_p), ("mdot", C.c_void_p)]
+                ("partial", C.c_void_p), ("mdot", C.c_void_p), ("motion", C.c_int32)]
 
 
 class Bins(C.Structure):

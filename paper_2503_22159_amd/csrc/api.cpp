@@ -103,6 +103,8 @@ d4dgs_status check_camera(const d4dgs_camera *c) {
 }
 
 d4dgs_status check_splats(const d4dgs_splats *sp, int n) {
+    if (sp && (sp->motion < D4DGS_MOTION_LINEAR || sp->motion > D4DGS_MOTION_FROZEN_J))
+        return fail(D4DGS_ERR_INVALID_ARG, "splats->motion is not a d4dgs_motion");
     if (!sp) return fail(D4DGS_ERR_INVALID_ARG, "splats is NULL");
     if (sp->capacity < n) return fail(D4DGS_ERR_OUT_OF_MEMORY, "splats capacity smaller than n");
     if (n > 0 && (!sp->rec || !sp->count || !sp->offset || !sp->partial))
@@ -169,7 +171,7 @@ d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, fl
         }
     }
     const hipError_t e = launch_project(sk, ck, t, mode, crec, ccap, (float4 *)splats->rec, splats->count,
-                                        splats->partial, (float2 *)splats->mdot, (hipStream_t)stream);
+                                        splats->partial, (float2 *)splats->mdot, splats->motion, (hipStream_t)stream);
     if (e != hipSuccess) {
         if (cache) cache->valid = 0;
         return hip_status(e, "d4dgs_project");
@@ -275,7 +277,8 @@ d4dgs_status render_bwd_impl(const d4dgs_scene *scene, const d4dgs_camera *cam, 
                                     dL_dflow, (float4 *)inst_grads, bins->capacity, (hipStream_t)stream);
     if (e == hipSuccess)
         e = launch_project_bwd(sk, ck, t, (const float4 *)splats->rec, splats->count, splats->offset,
-                               (const float4 *)inst_grads, bins->capacity, *grads, (hipStream_t)stream);
+                               (const float4 *)inst_grads, bins->capacity, *grads, splats->motion,
+                               (hipStream_t)stream);
     return hip_status(e, "d4dgs_render_bwd");
 }
 
@@ -381,6 +384,8 @@ d4dgs_status d4dgs_render_times(const d4dgs_scene *scene, const d4dgs_camera *ca
         D4_TRY(check_splats(&splats[i], scene->n));
         D4_TRY(check_bins(&bins[i]));
         if (!workspace[i] || !img[i]) return fail(D4DGS_ERR_INVALID_ARG, "render_times: NULL frame buffer");
+        if (splats[i].motion != splats[0].motion)
+            return fail(D4DGS_ERR_INVALID_ARG, "render_times: frames with different motion models");
         if (workspace_bytes < sort_workspace_bytes(scene->n, bins[i].capacity, tiles))
             return fail(D4DGS_ERR_OUT_OF_MEMORY, "render_times: workspace smaller than d4dgs_workspace_size");
     }
@@ -416,6 +421,7 @@ d4dgs_status d4dgs_render_times(const d4dgs_scene *scene, const d4dgs_camera *ca
     // time stages, kMaxTimes frames per launch; the first launch runs the camera stage
     for (int c0 = 0; c0 < T && e == hipSuccess; c0 += kMaxTimes) {
         TimesArgs a;
+        a.motion = splats[0].motion;
         a.nt = std::min(kMaxTimes, T - c0);
         for (int f = 0; f < a.nt; ++f) {
             const d4dgs_splats &sp = splats[c0 + f];

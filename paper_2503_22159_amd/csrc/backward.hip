@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
                                                         const uint32_t *__restrict__ count,
                                                         const uint32_t *__restrict__ offset,
                                                         const float4 *__restrict__ ig, uint32_t capacity,
-                                                        d4dgs_grads out) {
+                                                        d4dgs_grads out, int motion) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int n = s.n;
     // the block's drawn Gaussians (count > 0), compacted in LDS so that the busy
@@ -401,8 +401,11 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     const float w = expf(-0.5f * ((tau * tau) / (st * st)));
     const float pt[3] = {p[0] + tau * u[0], p[1] + tau * u[1], p[2] + tau * u[2]};
     const float md[2] = {(c.fx * u[0]) / p[2], (c.fy * u[1]) / p[2]};
-    const float z = pt[2];
-    float rx = pt[0] / z, ry = pt[1] / z;
+    // the point the Jacobian is taken at: the moved mean, or the camera stage's mean
+    const bool frozen = motion == D4DGS_MOTION_FROZEN_J, exact = motion == D4DGS_MOTION_EXACT;
+    const float *pj = frozen ? p : pt;
+    const float z = pj[2];
+    float rx = pj[0] / z, ry = pj[1] / z;
     const bool clx = rx > c.limx || rx < -c.limx, cly = ry > c.limy || ry < -c.limy;
     rx = fminf(c.limx, fmaxf(-c.limx, rx));
     ry = fminf(c.limy, fmaxf(-c.limy, ry));
@@ -441,29 +444,47 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 3; ++j) gJ[i][j] = 2.f * (Gp[i][0] * JV[0][j] + Gp[i][1] * JV[1][j]);
     const float z2 = z * z, z3 = z2 * z;
-    float g_pt[3] = {0.f, 0.f, 0.f};
-    g_pt[2] += gJ[0][0] * (-c.fx / z2) + gJ[0][2] * (2.f * c.fx * tx / z3) + gJ[1][1] * (-c.fy / z2) +
+    float g_pj[3] = {0.f, 0.f, 0.f};  // through the Jacobian's point
+    g_pj[2] += gJ[0][0] * (-c.fx / z2) + gJ[0][2] * (2.f * c.fx * tx / z3) + gJ[1][1] * (-c.fy / z2) +
                gJ[1][2] * (2.f * c.fy * ty / z3);
     const float g_tx = gJ[0][2] * (-c.fx / z2), g_ty = gJ[1][2] * (-c.fy / z2);
-    if (clx) g_pt[2] += g_tx * rx; else g_pt[0] += g_tx;
-    if (cly) g_pt[2] += g_ty * ry; else g_pt[1] += g_ty;
-    // p_t = p + tau u ; m = m0 + tau md
-    float g_p[3], g_u[3];
+    if (clx) g_pj[2] += g_tx * rx; else g_pj[0] += g_tx;
+    if (cly) g_pj[2] += g_ty * ry; else g_pj[1] += g_ty;
+    float g_pt[3], g_p[3], g_u[3] = {0.f, 0.f, 0.f};
     for (int i = 0; i < 3; ++i) {
-        g_p[i] = g_pt[i];
-        g_u[i] = tau * g_pt[i];
+        g_pt[i] = frozen ? 0.f : g_pj[i];
+        g_p[i] = frozen ? g_pj[i] : 0.f;
+    }
+    const float ipz = 1.f / p[2];
+    if (exact) {
+        // m = f pt_xy / pt_z + c; the flow velocity vel = f (u_xy pt_z - pt_xy u_z) / pt_z^2
+        const float zt = pt[2], izt = 1.f / zt, izt2 = izt * izt;
+        g_pt[0] += c.fx * gmx * izt - c.fx * u[2] * gfx * izt2;
+        g_pt[1] += c.fy * gmy * izt - c.fy * u[2] * gfy * izt2;
+        g_pt[2] += -(c.fx * pt[0] * gmx + c.fy * pt[1] * gmy) * izt2 +
+                   (c.fx * (2.f * pt[0] * u[2] - u[0] * zt) * gfx + c.fy * (2.f * pt[1] * u[2] - u[1] * zt) * gfy) *
+                       izt2 * izt;
+        g_u[0] += c.fx * gfx * izt;
+        g_u[1] += c.fy * gfy * izt;
+        g_u[2] += -(c.fx * pt[0] * gfx + c.fy * pt[1] * gfy) * izt2;
+    } else {
+        // m = m0 + tau md; the flow velocity is md.  Camera stage: m0 = f p_xy / p_z + c,
+        // md = f u_xy / p_z
+        g_tau += md[0] * gmx + md[1] * gmy;
+        const float g_mdx = tau * gmx + gfx, g_mdy = tau * gmy + gfy;
+        g_p[0] += c.fx * gmx * ipz;
+        g_p[1] += c.fy * gmy * ipz;
+        g_p[2] += -(c.fx * p[0] * gmx + c.fy * p[1] * gmy) * ipz * ipz;
+        g_u[0] += c.fx * g_mdx * ipz;
+        g_u[1] += c.fy * g_mdy * ipz;
+        g_p[2] += -(c.fx * u[0] * g_mdx + c.fy * u[1] * g_mdy) * ipz * ipz;
+    }
+    // p_t = p + tau u
+    for (int i = 0; i < 3; ++i) {
+        g_p[i] += g_pt[i];
+        g_u[i] += tau * g_pt[i];
     }
     g_tau += u[0] * g_pt[0] + u[1] * g_pt[1] + u[2] * g_pt[2];
-    g_tau += md[0] * gmx + md[1] * gmy;
-    const float g_mdx = tau * gmx + gfx, g_mdy = tau * gmy + gfy;
-    // camera stage: m0 = f p_xy / p_z + c ; md = f u_xy / p_z
-    const float ipz = 1.f / p[2];
-    g_p[0] += c.fx * gmx * ipz;
-    g_p[1] += c.fy * gmy * ipz;
-    g_p[2] += -(c.fx * p[0] * gmx + c.fy * p[1] * gmy) * ipz * ipz;
-    g_u[0] += c.fx * g_mdx * ipz;
-    g_u[1] += c.fy * g_mdy * ipz;
-    g_p[2] += -(c.fx * u[0] * g_mdx + c.fy * u[1] * g_mdy) * ipz * ipz;
     // p = R mu + T, u = R v
     float g_mu[3], g_v[3];
     for (int j = 0; j < 3; ++j) {
@@ -598,14 +619,14 @@ hipError_t launch_blend_bwd(const float4 *rec, const uint32_t *offset, const uin
 
 hipError_t launch_project_bwd(const SceneK &s, const CamK &c, float t, const float4 *rec, const uint32_t *count,
                               const uint32_t *offset, const float4 *inst_grads, int64_t capacity,
-                              const d4dgs_grads &g, hipStream_t st) {
+                              const d4dgs_grads &g, int motion, hipStream_t st) {
     if (s.n == 0) return hipSuccess;
     const int grid = (s.n + kBlock - 1) / kBlock;
     switch (s.deg) {
-        case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g); break;
-        case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g); break;
-        case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g); break;
-        default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g); break;
+        case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g, motion); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g, motion); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g, motion); break;
+        default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g, motion); break;
     }
     return hipGetLastError();
 }

@@ -153,7 +153,8 @@ SceneK make_scenek(const d4dgs_scene &s);
 
 // mode 0: camera + time stage, no record; 1: camera + time stage, writes record; 2: time stage from record
 hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, float *cam_rec, int cam_cap,
-                          float4 *rec, uint32_t *count, uint32_t *block_sums, float2 *mdot, hipStream_t st);
+                          float4 *rec, uint32_t *count, uint32_t *block_sums, float2 *mdot, int motion,
+                          hipStream_t st);
 
 // One request of a batched projection (kernel argument, by value).
 struct ReqK {
@@ -180,6 +181,7 @@ struct FrameK {
 constexpr int kMaxTimes = 16;  // frames per multi-timestamp projection launch
 struct TimesArgs {
     int nt;
+    int motion;  // d4dgs_motion of every frame
     FrameK f[kMaxTimes];
 };
 // mode as launch_project (0: no cache, 1: fill the cache, 2: from the cache)
@@ -221,7 +223,7 @@ hipError_t launch_flow_loss(const float *img, const float *flow, int W, int H, f
 
 hipError_t launch_project_bwd(const SceneK &s, const CamK &c, float t, const float4 *rec, const uint32_t *count,
                               const uint32_t *offset, const float4 *inst_grads, int64_t capacity,
-                              const d4dgs_grads &g, hipStream_t st);
+                              const d4dgs_grads &g, int motion, hipStream_t st);
 
 void set_error(const std::string &msg);
 

@@ -148,8 +148,12 @@ __device__ __forceinline__ void camera_stage(const GParams<DEG> &P, const CamK &
 }
 
 // Time stage.  Returns the tile count (0 = culled) and fills the splat record.
+// motion: D4DGS_MOTION_LINEAR (m = m0 + tau mdot, Jacobian at the moved mean),
+// D4DGS_MOTION_EXACT (m = projection of the moved mean), D4DGS_MOTION_FROZEN_J (linear
+// motion, Jacobian at the camera stage's mean).  vel receives the 2D mean's velocity at t.
 __device__ __forceinline__ uint32_t time_stage(const CamRec &cr, float o_, float mut, float st, float t,
-                                               const CamK &c, float4 &r0, float4 &r1, float4 &r2) {
+                                               const CamK &c, float4 &r0, float4 &r1, float4 &r2, int motion,
+                                               float2 &vel) {
     const float tau = t - mut;
     if (tau * tau > kTemporalCull * (st * st)) return 0;  // temporal weight below 1/255
     const float pz = cr.p[2];
@@ -157,14 +161,25 @@ __device__ __forceinline__ uint32_t time_stage(const CamRec &cr, float o_, float
     const float pty = cr.p[1] + tau * cr.u[1];
     const float z = pz + tau * cr.u[2];
     if (pz <= c.znear || z <= c.znear) return 0;
-    const float mx = cr.m0[0] + tau * cr.md[0];
-    const float my = cr.m0[1] + tau * cr.md[1];
-    float rx = ptx / z, ry = pty / z;
+    float mx, my;
+    if (motion == D4DGS_MOTION_EXACT) {
+        mx = (c.fx * ptx) / z + c.cx;
+        my = (c.fy * pty) / z + c.cy;
+        vel = make_float2((c.fx * (cr.u[0] * z - ptx * cr.u[2])) / (z * z),
+                          (c.fy * (cr.u[1] * z - pty * cr.u[2])) / (z * z));
+    } else {
+        mx = cr.m0[0] + tau * cr.md[0];
+        my = cr.m0[1] + tau * cr.md[1];
+        vel = make_float2(cr.md[0], cr.md[1]);
+    }
+    const bool frozen = motion == D4DGS_MOTION_FROZEN_J;
+    const float jx = frozen ? cr.p[0] : ptx, jy = frozen ? cr.p[1] : pty, jz = frozen ? pz : z;
+    float rx = jx / jz, ry = jy / jz;
     rx = fminf(c.limx, fmaxf(-c.limx, rx));
     ry = fminf(c.limy, fmaxf(-c.limy, ry));
-    const float tx = rx * z, ty = ry * z;
-    const float J00 = c.fx / z, J11 = c.fy / z;
-    const float J02 = -((c.fx * tx) / (z * z)), J12 = -((c.fy * ty) / (z * z));
+    const float tx = rx * jz, ty = ry * jz;
+    const float J00 = c.fx / jz, J11 = c.fy / jz;
+    const float J02 = -((c.fx * tx) / (jz * jz)), J12 = -((c.fy * ty) / (jz * jz));
     const float *C = cr.cv;  // 00 01 02 11 12 22
     const float T00 = J00 * C[0] + J02 * C[2];
     const float T02 = J00 * C[2] + J02 * C[5];
@@ -225,7 +240,7 @@ template <int MODE, int DEG>
 __global__ __launch_bounds__(kBlock) void k_project(SceneK s, CamK c, float t, float *__restrict__ cam_rec,
                                                    int cap, float4 *__restrict__ rec,
                                                    uint32_t *__restrict__ count, uint32_t *__restrict__ block_sums,
-                                                   float2 *__restrict__ mdot) {
+                                                   float2 *__restrict__ mdot, int motion) {
     const int gi = blockIdx.x * kBlock + threadIdx.x;
     uint32_t cnt = 0;
     if (gi < s.n) {
@@ -282,10 +297,11 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneK s, CamK c, float t, f
         }
         if (ok) {
             float4 r0, r1, r2;
-            cnt = time_stage(cr, s.opacity[gi], s.t_mean[gi], s.t_scale[gi], t, c, r0, r1, r2);
+            float2 vel;
+            cnt = time_stage(cr, s.opacity[gi], s.t_mean[gi], s.t_scale[gi], t, c, r0, r1, r2, motion, vel);
             if (cnt) {
                 store_rec(rec, gi, r0, r1, r2);
-                if (mdot) mdot[gi] = make_float2(cr.md[0], cr.md[1]);  // dm/dt (Eq. 13)
+                if (mdot) mdot[gi] = vel;  // dm/dt at t
             }
         }
         count[gi] = cnt;
@@ -318,7 +334,8 @@ __global__ __launch_bounds__(kBlock) void k_project_batch(SceneK s, BatchArgs ar
             CamRec cr;
             camera_stage<DEG>(P, q.cam, cr);
             float4 r0, r1, r2;
-            cnt = time_stage(cr, op, mut, st, q.t, q.cam, r0, r1, r2);
+            float2 vel;
+            cnt = time_stage(cr, op, mut, st, q.t, q.cam, r0, r1, r2, D4DGS_MOTION_LINEAR, vel);
             if (cnt) store_rec(q.rec, gi, r0, r1, r2);
         }
         if (valid) q.count[gi] = cnt;
@@ -396,7 +413,8 @@ __global__ __launch_bounds__(kBlock) void k_project_times(SceneK s, CamK c, floa
         uint32_t cnt = 0;
         if (valid && ok) {
             float4 r0, r1, r2;
-            cnt = time_stage(cr, op, mut, st, q.t, c, r0, r1, r2);
+            float2 vel;
+            cnt = time_stage(cr, op, mut, st, q.t, c, r0, r1, r2, args.motion, vel);
             if (cnt) store_rec(q.rec, gi, r0, r1, r2);
         }
         if (valid) q.count[gi] = cnt;
@@ -407,12 +425,13 @@ __global__ __launch_bounds__(kBlock) void k_project_times(SceneK s, CamK c, floa
 }  // namespace
 
 hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, float *cam_rec, int cam_cap,
-                          float4 *rec, uint32_t *count, uint32_t *block_sums, float2 *mdot, hipStream_t st) {
+                          float4 *rec, uint32_t *count, uint32_t *block_sums, float2 *mdot, int motion,
+                          hipStream_t st) {
     if (s.n == 0) return hipSuccess;
     const int grid = (s.n + kBlock - 1) / kBlock;
 #define D4_LAUNCH(M, D)                                                                                  \
     hipLaunchKernelGGL((k_project<M, D>), dim3(grid), dim3(kBlock), 0, st, s, c, t, cam_rec, cam_cap, rec, \
-                       count, block_sums, mdot)
+                       count, block_sums, mdot, motion)
     if (mode == 2) {
         D4_LAUNCH(2, 0);
     } else {

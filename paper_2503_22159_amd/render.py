@@ -66,8 +66,9 @@ class DeviceScene:
 class FrameState:
     """Device buffers of one rendered frame (splat record, sorted bins, replay state)."""
 
-    def __init__(self, n, width, height, capacity, device="cuda", flow=False):
+    def __init__(self, n, width, height, capacity, device="cuda", flow=False, motion=0):
         self.n, self.width, self.height, self.capacity = n, width, height, int(capacity)
+        self.motion = int(motion)  # d4dgs_motion of the time stage
         dev = device
         nn = max(n, 1)
         self.rec = torch.empty(nn * B.REC_FLOATS, dtype=torch.float32, device=dev)
@@ -94,6 +95,7 @@ class FrameState:
         s.rec, s.count, s.offset, s.partial = (self.rec.data_ptr(), self.count.data_ptr(),
                                                self.offset.data_ptr(), self.partial.data_ptr())
         s.mdot = self.mdot.data_ptr() if self.mdot is not None else None
+        s.motion = self.motion
         return s
 
     def bins(self):
@@ -162,16 +164,17 @@ def blend(st: FrameState, bg=(0.0, 0.0, 0.0), keep_state=True, img=None):
 
 
 def render_forward(scene: DeviceScene, cam, t, bg=(0.0, 0.0, 0.0), capacity=None, keep_state=True,
-                   cache: CamCache | None = None):
+                   cache: CamCache | None = None, motion=0):
     """Full forward with exact instance capacity handling (synchronises once to read the
     instance count; grows the capacity and re-sorts on overflow)."""
     cap = capacity or default_capacity(scene.n, cam.width, cam.height)
-    st = FrameState(scene.n, cam.width, cam.height, cap, scene.t["mean"].device)
+    st = FrameState(scene.n, cam.width, cam.height, cap, scene.t["mean"].device, motion=motion)
     project(scene, cam, t, st, cache)
     ni = bin_sort(st, sync=True)
     if ni > st.capacity:
         # the scan consumed the per-block sums in place: project again into larger buffers
-        st = FrameState(scene.n, cam.width, cam.height, int(ni * 1.25) + 1024, scene.t["mean"].device)
+        st = FrameState(scene.n, cam.width, cam.height, int(ni * 1.25) + 1024, scene.t["mean"].device,
+                        motion=motion)
         project(scene, cam, t, st, cache)
         ni2 = bin_sort(st, sync=True)
         assert ni2 == ni
@@ -222,16 +225,16 @@ def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, gra
 
 
 def render_forward_flow(scene: DeviceScene, cam, t, bg=(0.0, 0.0, 0.0), capacity=None, keep_state=True,
-                        cache: CamCache | None = None):
+                        cache: CamCache | None = None, motion=0):
     """Forward render with the optical flow of Sec. 3.3 (each splat's screen velocity
     blended with the colour weights).  Returns (img [3,H,W], flow [2,H,W], state)."""
     cap = capacity or default_capacity(scene.n, cam.width, cam.height)
     dev = scene.t["mean"].device
-    st = FrameState(scene.n, cam.width, cam.height, cap, dev, flow=True)
+    st = FrameState(scene.n, cam.width, cam.height, cap, dev, flow=True, motion=motion)
     project(scene, cam, t, st, cache)
     ni = bin_sort(st, sync=True)
     if ni > st.capacity:
-        st = FrameState(scene.n, cam.width, cam.height, int(ni * 1.25) + 1024, dev, flow=True)
+        st = FrameState(scene.n, cam.width, cam.height, int(ni * 1.25) + 1024, dev, flow=True, motion=motion)
         project(scene, cam, t, st, cache)
         assert bin_sort(st, sync=True) == ni
     st.num_instances = ni

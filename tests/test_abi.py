@@ -37,7 +37,7 @@ def test_binding_structs_match_header_sizes():
     # sizes implied by the header's field lists (LP64)
     assert C.sizeof(B.Camera) == 4 * 2 + 4 * 7 + 4 * 9 + 4 * 3 + 4 * 3
     assert C.sizeof(B.Scene) == 8 + 8 * 8
-    assert C.sizeof(B.Splats) == 8 + 8 * 5  # capacity (padded), rec, count, offset, partial, mdot
+    assert C.sizeof(B.Splats) == 8 + 8 * 5 + 8  # capacity (padded), 5 pointers, motion (padded)
     assert C.sizeof(B.Bins) == 8 + 8 * 4
     assert B.lib.d4dgs_abi_version() == B.ABI_VERSION
     assert set(B.EXPORTS) == set(declared_functions())
