@@ -375,12 +375,6 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     Rq[7] = 2.0f * (qy * qz + qw * qx);
     Rq[8] = 1.0f - 2.0f * (qx * qx + qy * qy);
     const float sc[3] = {s.scale[gi], s.scale[n + gi], s.scale[2 * n + gi]};
-    float M[9], Sg[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) M[3 * i + j] = Rq[3 * i + j] * sc[j];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            Sg[3 * i + j] = M[3 * i + 0] * M[3 * j + 0] + M[3 * i + 1] * M[3 * j + 1] + M[3 * i + 2] * M[3 * j + 2];
     const float mu[3] = {s.mean[gi], s.mean[n + gi], s.mean[2 * n + gi]};
     const float v[3] = {s.velocity[gi], s.velocity[n + gi], s.velocity[2 * n + gi]};
     const float *R = c.R;
@@ -389,13 +383,6 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
         p[i] = R[3 * i + 0] * mu[0] + R[3 * i + 1] * mu[1] + R[3 * i + 2] * mu[2] + c.T[i];
         u[i] = R[3 * i + 0] * v[0] + R[3 * i + 1] * v[1] + R[3 * i + 2] * v[2];
     }
-    float A3[9], V[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            A3[3 * i + j] = R[3 * i + 0] * Sg[j] + R[3 * i + 1] * Sg[3 + j] + R[3 * i + 2] * Sg[6 + j];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            V[3 * i + j] = A3[3 * i + 0] * R[3 * j + 0] + A3[3 * i + 1] * R[3 * j + 1] + A3[3 * i + 2] * R[3 * j + 2];
     const float op = s.opacity[gi], mut = s.t_mean[gi], st = s.t_scale[gi];
     const float tau = t - mut;
     const float w = expf(-0.5f * ((tau * tau) / (st * st)));
@@ -421,28 +408,39 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     const float g_w = op * gam;
     float g_tau = g_w * (-w * tau / (st * st));
     float g_st = g_w * (w * tau * tau / (st * st * st));
-    // conic = inverse(S2), S2 = [[a, b], [b, c]]:  dS2 = -Q dQ Q
+    // covariance.  The forward's 2D covariance is Sigma' = J V J^T + dilation with
+    // V = sum_j s_j^2 w_j w_j^T, w_j = R Rq e_j (axis j of the Gaussian in the camera
+    // frame), i.e. Sigma' - dilation = sum_j s_j^2 a_j a_j^T with a_j = J w_j, and the
+    // conic is Q = Sigma'^-1, so dQ = -Q dSigma' Q.  With G_Q = dL/dQ (symmetric, off
+    // diagonal gB / 2), n_j = Q a_j and c_j = -Q G_Q n_j:
+    //   dL/ds_j = -2 s_j n_j . (G_Q n_j),   dL/da_j = 2 s_j^2 c_j,
+    // and a_j = J w_j passes that on to J (dL/dJ = sum_j 2 s_j^2 c_j w_j^T) and to w_j
+    // (2 s_j^2 J^T c_j), hence to Rq (R^T of it).  Contracting with n_j before any 2x2 or
+    // 3x3 gradient matrix is formed keeps elongated splats accurate: their conic is
+    // nearly singular, Q a_j is small along the long axis, and forming -Q G_Q Q first
+    // would cancel down to that size in FP32.
     const float h = 0.5f * gB;
-    const float g_a = -(QA * QA * gA + 2.f * QA * QB * h + QB * QB * gC);
-    const float g_c = -(QB * QB * gA + 2.f * QB * QC * h + QC * QC * gC);
-    const float g_b2 = -(QA * QB * gA + (QB * QB + QA * QC) * h + QB * QC * gC);  // half of d/db
-    // Sigma' = J V J^T with gradient matrix Gp = [[g_a, g_b2], [g_b2, g_c]]
-    const float J[2][3] = {{J00, 0.f, J02}, {0.f, J11, J12}};
-    const float Gp[2][2] = {{g_a, g_b2}, {g_b2, g_c}};
-    // g_V = J^T Gp J
-    float GJ[2][3];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 3; ++j) GJ[i][j] = Gp[i][0] * J[0][j] + Gp[i][1] * J[1][j];
-    float gV[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) gV[3 * i + j] = J[0][i] * GJ[0][j] + J[1][i] * GJ[1][j];
-    // g_J = 2 Gp J V
-    float JV[2][3];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 3; ++j) JV[i][j] = J[i][0] * V[j] + J[i][1] * V[3 + j] + J[i][2] * V[6 + j];
-    float gJ[2][3];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 3; ++j) gJ[i][j] = 2.f * (Gp[i][0] * JV[0][j] + Gp[i][1] * JV[1][j]);
+    float gJ[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float g_s[3], gRq[9];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        float wj[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) wj[i] = R[3 * i + 0] * Rq[j] + R[3 * i + 1] * Rq[3 + j] + R[3 * i + 2] * Rq[6 + j];
+        const float ax = J00 * wj[0] + J02 * wj[2], ay = J11 * wj[1] + J12 * wj[2];
+        const float nx = QA * ax + QB * ay, ny = QB * ax + QC * ay;
+        const float mx = gA * nx + h * ny, my = h * nx + gC * ny;
+        g_s[j] = -2.f * sc[j] * (nx * mx + ny * my);
+        const float cx = -(QA * mx + QB * my), cy = -(QB * mx + QC * my);
+        const float s2 = 2.f * sc[j] * sc[j];
+        gJ[0][0] += s2 * cx * wj[0];
+        gJ[0][2] += s2 * cx * wj[2];
+        gJ[1][1] += s2 * cy * wj[1];
+        gJ[1][2] += s2 * cy * wj[2];
+        const float gw[3] = {s2 * (J00 * cx), s2 * (J11 * cy), s2 * (J02 * cx + J12 * cy)};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gRq[3 * k + j] = R[k] * gw[0] + R[3 + k] * gw[1] + R[6 + k] * gw[2];
+    }
     const float z2 = z * z, z3 = z2 * z;
     float g_pj[3] = {0.f, 0.f, 0.f};  // through the Jacobian's point
     g_pj[2] += gJ[0][0] * (-c.fx / z2) + gJ[0][2] * (2.f * c.fx * tx / z3) + gJ[1][1] * (-c.fy / z2) +
@@ -491,23 +489,6 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
         g_mu[j] = R[j] * g_p[0] + R[3 + j] * g_p[1] + R[6 + j] * g_p[2];
         g_v[j] = R[j] * g_u[0] + R[3 + j] * g_u[1] + R[6 + j] * g_u[2];
     }
-    // V = R Sigma R^T  ->  g_Sigma = R^T gV R
-    float tmp[9], gS[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) tmp[3 * i + j] = R[i] * gV[j] + R[3 + i] * gV[3 + j] + R[6 + i] * gV[6 + j];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) gS[3 * i + j] = tmp[3 * i + 0] * R[j] + tmp[3 * i + 1] * R[3 + j] + tmp[3 * i + 2] * R[6 + j];
-    // Sigma = M M^T -> g_M = (gS + gS^T) M
-    float gM[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            float acc = 0.f;
-            for (int k = 0; k < 3; ++k) acc += (gS[3 * i + k] + gS[3 * k + i]) * M[3 * k + j];
-            gM[3 * i + j] = acc;
-        }
-    float g_s[3], gRq[9];
-    for (int j = 0; j < 3; ++j) g_s[j] = gM[j] * Rq[j] + gM[3 + j] * Rq[3 + j] + gM[6 + j] * Rq[6 + j];
-    for (int i = 0; i < 9; ++i) gRq[i] = gM[i] * sc[i % 3];
     // rotation matrix of the unit quaternion (w, x, y, z)
     float gqw = 2.f * (-qz * gRq[1] + qy * gRq[2] + qz * gRq[3] - qx * gRq[5] - qy * gRq[6] + qx * gRq[7]);
     float gqx = 2.f * (qy * gRq[1] + qz * gRq[2] + qy * gRq[3] - 2.f * qx * gRq[4] - qw * gRq[5] + qz * gRq[6] +

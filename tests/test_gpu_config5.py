@@ -1,0 +1,126 @@
+"""The large training-style step at full size: 2M Gaussians (128-cluster mixture, SH3),
+a batch of 4 views at 2704x2028 with distinct t, forward + backward, checked against the
+oracle on what it can compute at this size.
+
+* projection: every Gaussian of every view, bit-exact where the FP contract says so;
+* binning and sort: every instance of every view, bit-exact (keys, values, ranges);
+* image: a sample of tiles (random ones plus the ragged last row and column), which the
+  oracle blends alone by giving every other tile an empty range (a tile's pixels depend
+  only on that tile's list);
+* gradients: the upstream gradient is non-zero only on the sampled tiles, so the
+  adjoint of the whole frame equals the oracle's adjoint of those tiles; the gradients
+  of all 4 views accumulate into one set, compared per parameter group at the 1e-3
+  relative bar.  The peak device memory of the step is printed."""
+import numpy as np
+import pytest
+
+import oracle
+from _helpers import assert_bins_equal, assert_projection_equal, compare_images, decode_record, read_bins
+from paper_2503_22159_amd import inputs
+from test_gpu_backward import GROUPS, compare_group
+
+pytestmark = pytest.mark.gpu
+
+N_SAMPLED = 192
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2503_22159_amd import render
+
+    return render
+
+
+@pytest.fixture(scope="module")
+def scene():
+    return inputs.config5_scene()
+
+
+def sampled_tiles(cam, seed):
+    TX = (cam.width + 15) // 16
+    TY = (cam.height + 15) // 16
+    rng = np.random.default_rng(seed)
+    keep = np.zeros(TX * TY, bool)
+    keep[rng.choice(TX * TY, N_SAMPLED, replace=False)] = True
+    keep[(TY - 1) * TX + rng.choice(TX, 8, replace=False)] = True      # ragged bottom row
+    keep[rng.choice(TY, 8, replace=False) * TX + (TX - 1)] = True      # ragged right column
+    keep[TX * TY - 1] = True                                           # the corner tile
+    pix = np.repeat(np.repeat(keep.reshape(TY, TX), 16, axis=0), 16, axis=1)[: cam.height, : cam.width]
+    return keep, pix
+
+
+def masked_bins(bins, keep):
+    r = bins["ranges"].copy()
+    r[~keep, 1] = r[~keep, 0]
+    out = dict(bins)
+    out["ranges"] = r
+    return out
+
+
+@pytest.mark.timeout(400)
+def test_config5_batch_forward_backward(R, scene):
+    import torch
+
+    views = inputs.config5_views()
+    ds = R.DeviceScene.from_inputs(scene)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+
+    # forward of the 4 views, states kept for the backward (no per-splat blend state)
+    states = []
+    for cam, t in views:
+        img, st = R.render_forward(ds, cam, t, (0.0, 0.0, 0.0))
+        states.append((img, st))
+    grads = R.grads_like(ds)
+    ups = []
+    for i, (cam, t) in enumerate(views):
+        keep, pix = sampled_tiles(cam, 50 + i)
+        ups.append((keep, pix))
+    # the oracle's sampled blend decides which pixels are flagged; the upstream gradient
+    # is zero there and off the sampled tiles
+    orc = []
+    for i, (cam, t) in enumerate(views):
+        keep, pix = ups[i]
+        proj = oracle.project(scene, cam, t, "f32")
+        bins = oracle.bin(proj, cam)
+        mb = masked_bins(bins, keep)
+        res = oracle.blend(proj, mb, cam)
+        dL = inputs.upstream_grad(70 + i, cam.width, cam.height) * (pix & ~(res["flags"] > 0))[None]
+        orc.append((proj, bins, mb, res, dL))
+    for i, (cam, t) in enumerate(views):
+        _, st = states[i]
+        R.render_backward(ds, cam, t, (0.0, 0.0, 0.0), st, torch.from_numpy(orc[i][4]).cuda(), grads)
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated() - base
+    print(f"config5 step: scene {base / 2**30:.2f} GiB resident, peak step memory {peak / 2**30:.2f} GiB")
+
+    gsum = None
+    for i, (cam, t) in enumerate(views):
+        img, st = states[i]
+        proj, bins, mb, res, dL = orc[i]
+        keep, pix = ups[i]
+        gp = decode_record(st, scene.n)
+        assert_projection_equal(gp, proj)
+        gb = read_bins(st)
+        assert_bins_equal(gb, bins)
+        # image on the sampled tiles only: off the sample the oracle's values are replaced
+        # by the GPU's, and its flags cleared
+        gi = img.cpu().numpy()
+        gT = st.final_T.cpu().numpy()
+        gN = st.n_contrib.cpu().numpy().view(np.uint32)
+        ri = {"img": np.where(pix[None], res["img"], gi), "flags": np.where(pix, res["flags"], 0),
+              "final_T": np.where(pix, res["final_T"], gT), "n_contrib": np.where(pix, res["n_contrib"], gN)}
+        stats = compare_images(gi, gT, gN, ri)
+        print("config5 view", i, "instances", gb["I"], "sampled px", int(pix.sum()), stats)
+        gs = oracle.blend_bwd(proj, mb, cam, dL.astype(np.float64))
+        touched = (np.abs(gs["m"]).sum(0) + np.abs(gs["conic"]).sum(0) + np.abs(gs["amax"]) +
+                   np.abs(gs["rgb"]).sum(0)) > 0
+        gpar = oracle.project_bwd(scene, cam, t, touched.astype(np.int32), gs)
+        gsum = gpar if gsum is None else {k: gsum[k] + gpar[k] for k in gsum}
+    gg = {k: grads[k].cpu().numpy().astype(np.float64) for k in GROUPS}
+    errs = {k: compare_group(k, gg[k], gsum[k]) for k in GROUPS}
+    print("config5 grad rel err", errs)
