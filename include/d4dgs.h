@@ -219,6 +219,16 @@ d4dgs_status d4dgs_render_fwd(const d4dgs_splats *splats, const d4dgs_bins *bins
                               int32_t height, const float bg[3], float *img, float *final_T,
                               uint32_t *n_contrib, d4dgs_stream stream);
 
+/* d4dgs_render_fwd with the blend kernel timed: start_event and stop_event are
+ * hipEvent_t handles, created by the caller with timing enabled, and are set to the
+ * start and the end of the blend kernel itself (not of the stream position around
+ * it), so that hipEventElapsedTime(start, stop) is the kernel's duration.  For
+ * measurement; the output is that of d4dgs_render_fwd.  NULL events are an error. */
+d4dgs_status d4dgs_render_fwd_timed(const d4dgs_splats *splats, const d4dgs_bins *bins, int32_t width,
+                                    int32_t height, const float bg[3], float *img, float *final_T,
+                                    uint32_t *n_contrib, void *start_event, void *stop_event,
+                                    d4dgs_stream stream);
+
 /* Adjoint of d4dgs_project + d4dgs_render_fwd at the same (scene, camera, t) and the
  * same splats/bins/replay state.  dL_dimg (device) [3][height][width].  Replays each
  * pixel's transmittance backwards from final_T (no per-splat forward state), writes

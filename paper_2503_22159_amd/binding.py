@@ -83,7 +83,7 @@ class D4Error(RuntimeError):
 
 
 EXPORTS = ("d4dgs_abi_version", "d4dgs_last_error", "d4dgs_workspace_size", "d4dgs_project", "d4dgs_bin_sort",
-           "d4dgs_bin_sort_sync", "d4dgs_render_fwd", "d4dgs_render_bwd", "d4dgs_serve_create",
+           "d4dgs_bin_sort_sync", "d4dgs_render_fwd", "d4dgs_render_fwd_timed", "d4dgs_render_bwd", "d4dgs_serve_create",
            "d4dgs_serve_submit", "d4dgs_serve_poll", "d4dgs_serve_wait", "d4dgs_serve_stats_get",
            "d4dgs_serve_destroy", "d4dgs_render_times", "d4dgs_render_fwd_flow", "d4dgs_flow_loss_workspace_size",
            "d4dgs_flow_loss", "d4dgs_render_bwd_flow")
@@ -106,6 +106,8 @@ def _load():
                                           C.POINTER(Bins), C.POINTER(C.c_int64), P]),
         "d4dgs_render_fwd": (C.c_int, [C.POINTER(Splats), C.POINTER(Bins), C.c_int32, C.c_int32,
                                        C.POINTER(C.c_float * 3), P, P, P, P]),
+        "d4dgs_render_fwd_timed": (C.c_int, [C.POINTER(Splats), C.POINTER(Bins), C.c_int32, C.c_int32,
+                                             C.POINTER(C.c_float * 3), P, P, P, P, P, P]),
         "d4dgs_render_bwd": (C.c_int, [C.POINTER(Scene), C.POINTER(Camera), C.c_float, C.POINTER(Splats),
                                        C.POINTER(Bins), C.POINTER(C.c_float * 3), P, P, P, P, C.POINTER(Grads), P]),
         "d4dgs_serve_create": (C.c_int, [C.POINTER(Scene), C.POINTER(ServeConfig), C.POINTER(C.c_void_p)]),

@@ -228,9 +228,11 @@ d4dgs_status d4dgs_bin_sort_sync(const d4dgs_splats *splats, int32_t n, int32_t 
     return D4DGS_OK;
 }
 
-d4dgs_status d4dgs_render_fwd(const d4dgs_splats *splats, const d4dgs_bins *bins, int32_t width, int32_t height,
-                              const float bg[3], float *img, float *final_T, uint32_t *n_contrib,
-                              d4dgs_stream stream) {
+namespace {
+
+d4dgs_status render_fwd_impl(const d4dgs_splats *splats, const d4dgs_bins *bins, int32_t width, int32_t height,
+                             const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipEvent_t e0,
+                             hipEvent_t e1, d4dgs_stream stream) {
     if (!splats || !splats->rec) return fail(D4DGS_ERR_INVALID_ARG, "splats is NULL");
     D4_TRY(check_bins(bins));
     if (width <= 0 || height <= 0 || width > 65535 * kTile || height > 65535 * kTile)
@@ -244,8 +246,24 @@ d4dgs_status d4dgs_render_fwd(const d4dgs_splats *splats, const d4dgs_bins *bins
     dummy.height = height;
     const CamK ck = make_camk(dummy);
     const hipError_t e = launch_blend((const float4 *)splats->rec, bins->values, bins->ranges, ck, bg, img, final_T,
-                                      n_contrib, (hipStream_t)stream);
+                                      n_contrib, (hipStream_t)stream, e0, e1);
     return hip_status(e, "d4dgs_render_fwd");
+}
+
+}  // namespace
+
+d4dgs_status d4dgs_render_fwd(const d4dgs_splats *splats, const d4dgs_bins *bins, int32_t width, int32_t height,
+                              const float bg[3], float *img, float *final_T, uint32_t *n_contrib,
+                              d4dgs_stream stream) {
+    return render_fwd_impl(splats, bins, width, height, bg, img, final_T, n_contrib, nullptr, nullptr, stream);
+}
+
+d4dgs_status d4dgs_render_fwd_timed(const d4dgs_splats *splats, const d4dgs_bins *bins, int32_t width,
+                                    int32_t height, const float bg[3], float *img, float *final_T,
+                                    uint32_t *n_contrib, void *start_event, void *stop_event, d4dgs_stream stream) {
+    if (!start_event || !stop_event) return fail(D4DGS_ERR_INVALID_ARG, "start_event or stop_event is NULL");
+    return render_fwd_impl(splats, bins, width, height, bg, img, final_T, n_contrib, (hipEvent_t)start_event,
+                           (hipEvent_t)stop_event, stream);
 }
 
 }  // extern "C"

@@ -15,6 +15,8 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <hip/hip_ext.h>
+
 #include "internal.hpp"
 
 namespace d4 {
@@ -191,18 +193,31 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     }
 }
 
+// With events e0/e1 the launch goes through hipExtLaunchKernel, which sets them to the
+// kernel's own start and end (a stream-ordered event pair would also time the dispatch).
 template <int PX, int RW>
 void launch_px(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c, const float bg[3],
-               float *img, float *final_T, uint32_t *n_contrib, hipStream_t st) {
+               float *img, float *final_T, uint32_t *n_contrib, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int nlogical = c.TX * c.TY * (4 / PX);
     const int per_xcd = (nlogical + 7) / 8;
-    if (final_T)
-        hipLaunchKernelGGL((k_blend<PX, RW, true, false>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges,
-                           c, bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd, nullptr, nullptr);
-    else
-        hipLaunchKernelGGL((k_blend<PX, RW, false, false>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals,
-                           ranges, c, bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd, nullptr,
-                           nullptr);
+    const dim3 grid(per_xcd * 8), block(kWave);
+    if (final_T) {
+        if (e0)
+            hipExtLaunchKernelGGL((k_blend<PX, RW, true, false>), grid, block, 0, st, e0, e1, 0, rec, vals, ranges, c,
+                                  bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd,
+                                  (const float2 *)nullptr, (float *)nullptr);
+        else
+            hipLaunchKernelGGL((k_blend<PX, RW, true, false>), grid, block, 0, st, rec, vals, ranges, c, bg[0], bg[1],
+                               bg[2], img, final_T, n_contrib, nlogical, per_xcd, nullptr, nullptr);
+    } else {
+        if (e0)
+            hipExtLaunchKernelGGL((k_blend<PX, RW, false, false>), grid, block, 0, st, e0, e1, 0, rec, vals, ranges, c,
+                                  bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd,
+                                  (const float2 *)nullptr, (float *)nullptr);
+        else
+            hipLaunchKernelGGL((k_blend<PX, RW, false, false>), grid, block, 0, st, rec, vals, ranges, c, bg[0], bg[1],
+                               bg[2], img, final_T, n_contrib, nlogical, per_xcd, nullptr, nullptr);
+    }
 }
 
 // Wavefront pixel region: PX pixels per lane in one column, RW columns wide.  Default 1 x 8
@@ -221,14 +236,15 @@ int blend_variant() {
 }  // namespace
 
 hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c,
-                        const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st) {
+                        const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st,
+                        hipEvent_t e0, hipEvent_t e1) {
     if (c.TX * c.TY == 0) return hipSuccess;
     switch (blend_variant()) {
-        case 116: launch_px<1, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
-        case 208: launch_px<2, 8>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
-        case 216: launch_px<2, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
-        case 416: launch_px<4, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
-        default: launch_px<1, 8>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st); break;
+        case 116: launch_px<1, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st, e0, e1); break;
+        case 208: launch_px<2, 8>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st, e0, e1); break;
+        case 216: launch_px<2, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st, e0, e1); break;
+        case 416: launch_px<4, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st, e0, e1); break;
+        default: launch_px<1, 8>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st, e0, e1); break;
     }
     return hipGetLastError();
 }

@@ -204,8 +204,10 @@ hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *o
                            const CamK &c, const SortWs &ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
                            int64_t *num_inst, int64_t capacity, int32_t *d_status, hipStream_t st);
 
+// e0/e1 (optional): events set to the blend kernel's own start and end
 hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c,
-                        const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st);
+                        const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // the blend with the optical flow: mdot [n] per splat, flow [2][H][W]
 hipError_t launch_blend_flow(const float4 *rec, const float2 *mdot, const uint32_t *vals, const uint32_t *ranges,
                              const CamK &c, const float bg[3], float *img, float *flow, float *final_T,

@@ -388,10 +388,17 @@ class Renderer:
         B.check(B.lib.d4dgs_bin_sort(C.byref(self._sp), self.st.n, self.width, self.height, self._ws[0],
                                      self._ws[1], C.byref(self._bn), self._status, stream or _stream()))
 
-    def blend(self, bg=(0.0, 0.0, 0.0), stream=None):
-        B.check(B.lib.d4dgs_render_fwd(C.byref(self._sp), C.byref(self._bn), self.width, self.height,
-                                       C.byref(self._bg(bg)), self._img, self._state[0], self._state[1],
-                                       stream or _stream()))
+    def blend(self, bg=(0.0, 0.0, 0.0), stream=None, events=None):
+        """events: optional (start, stop) torch.cuda.Event pair (timing enabled), set to the
+        blend kernel's own start and end."""
+        if events is None:
+            B.check(B.lib.d4dgs_render_fwd(C.byref(self._sp), C.byref(self._bn), self.width, self.height,
+                                           C.byref(self._bg(bg)), self._img, self._state[0], self._state[1],
+                                           stream or _stream()))
+        else:
+            B.check(B.lib.d4dgs_render_fwd_timed(C.byref(self._sp), C.byref(self._bn), self.width, self.height,
+                                                 C.byref(self._bg(bg)), self._img, self._state[0], self._state[1],
+                                                 events[0].cuda_event, events[1].cuda_event, stream or _stream()))
         return self.img
 
     def render(self, cam, t, bg=(0.0, 0.0, 0.0)):

@@ -195,3 +195,37 @@ def test_invalid_arguments_rejected(R):
     r = B.lib.d4dgs_bin_sort(C.byref(st.splats()), sc.n, cam.width, cam.height, C.c_void_p(st.ws.data_ptr()), 16,
                              C.byref(st.bins()), None, R._stream())
     assert r == B.ERR_OUT_OF_MEMORY
+
+
+def test_timed_blend_matches_and_times_the_kernel(R):
+    """d4dgs_render_fwd_timed writes what d4dgs_render_fwd writes and sets its events to
+    the blend kernel's start and end (a positive duration); NULL events are rejected."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2503_22159_amd import binding as B
+
+    sc = inputs.config2_scene(n=30_000)
+    cam = inputs.arc_camera(5, width=337, height=253)
+    ds = R.DeviceScene.from_inputs(sc)
+    rend = R.Renderer(ds, cam.width, cam.height, keep_state=True)
+    rend.render(cam, np.float32(0.4), (0.1, 0.2, 0.3))
+    torch.cuda.synchronize()
+    ref = [rend.img.cpu().numpy(), rend.st.final_T.cpu().numpy(), rend.st.n_contrib.cpu().numpy()]
+    for a in (rend.img, rend.st.final_T, rend.st.n_contrib):
+        a.fill_(7)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    ev[0].record()
+    ev[1].record()
+    rend.blend((0.1, 0.2, 0.3), events=ev)
+    torch.cuda.synchronize()
+    got = [rend.img.cpu().numpy(), rend.st.final_T.cpu().numpy(), rend.st.n_contrib.cpu().numpy()]
+    for g, r in zip(got, ref):
+        assert np.array_equal(g, r)
+    ms = ev[0].elapsed_time(ev[1])
+    assert 0.0 < ms < 100.0, ms
+    r = B.lib.d4dgs_render_fwd_timed(C.byref(rend._sp), C.byref(rend._bn), cam.width, cam.height,
+                                     C.byref(rend._bg((0.0, 0.0, 0.0))), rend._img, None, None, None, None,
+                                     R._stream())
+    assert r == B.ERR_INVALID_ARG and "event" in B.last_error()
