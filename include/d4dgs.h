@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define D4DGS_ABI_VERSION 2
+#define D4DGS_ABI_VERSION 3
 #define D4DGS_TILE 16           /* tile edge in pixels */
 #define D4DGS_CAM_REC_FLOATS 19 /* camera-stage record: p3 u3 covc6 m0_2 md2 rgb3 */
 #define D4DGS_REC_FLOATS 12     /* splat record, 3 x float4 per Gaussian */
@@ -150,13 +150,22 @@ typedef struct {
  *   keys    [capacity] uint64 (tile << 32) | float-bits(depth), ascending
  *   values  [capacity] uint32 Gaussian index (ties in key by ascending index)
  *   ranges  [2 * tiles] uint32 [start, end) of each tile's list, tile = ty * TX + tx
- *   num_instances  one int64: total instances (may exceed capacity on overflow) */
+ *   num_instances  one int64: total instances (may exceed capacity on overflow)
+ *   order   [tiles] uint32, optional (NULL: not used): d4dgs_bin_sort writes the tiles
+ *           grouped by tile row mod 8 (group 0 first) and, inside a group, ordered by
+ *           list length, longest first (lengths in steps of 8, any order inside a
+ *           step); the per-tile kernels of d4dgs_bin_sort, d4dgs_render_fwd*,
+ *           d4dgs_render_bwd* and d4dgs_render_times then start on the long lists.
+ *           Scheduling only: results are identical with or without it.  The blends
+ *           need the order written by the d4dgs_bin_sort call of the same bins (entries
+ *           >= tiles are skipped, never read out of bounds). */
 typedef struct {
     int64_t capacity;
     uint64_t *keys;
     uint32_t *values;
     uint32_t *ranges;
     int64_t *num_instances;
+    uint32_t *order;
 } d4dgs_bins;
 
 /* Parameter gradients, same planar shapes as d4dgs_scene (all device, float32).

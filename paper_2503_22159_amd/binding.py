@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libd4dgs.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MOTION_LINEAR, MOTION_EXACT, MOTION_FROZEN_J = 0, 1, 2  # d4dgs_motion
 TILE = 16
 CAM_REC_FLOATS = 19
@@ -52,7 +52,7 @@ class Splats(C.Structure):
 
 class Bins(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("keys", C.c_void_p), ("values", C.c_void_p), ("ranges", C.c_void_p),
-                ("num_instances", C.c_void_p)]
+                ("num_instances", C.c_void_p), ("order", C.c_void_p)]
 
 
 class Grads(C.Structure):

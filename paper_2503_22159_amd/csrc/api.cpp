@@ -204,7 +204,7 @@ d4dgs_status d4dgs_bin_sort(const d4dgs_splats *splats, int32_t n, int32_t width
     const SortWs ws = carve_workspace(workspace, n, bins->capacity, ck.TX * ck.TY);
     const hipError_t e = launch_bin_sort((const float4 *)splats->rec, splats->count, splats->offset, splats->partial,
                                          n, ck, ws, bins->keys, bins->values, bins->ranges, bins->num_instances,
-                                         bins->capacity, d_status, (hipStream_t)stream);
+                                         bins->capacity, d_status, bins->order, (hipStream_t)stream);
     return hip_status(e, "d4dgs_bin_sort");
 }
 
@@ -245,8 +245,8 @@ d4dgs_status render_fwd_impl(const d4dgs_splats *splats, const d4dgs_bins *bins,
     dummy.width = width;
     dummy.height = height;
     const CamK ck = make_camk(dummy);
-    const hipError_t e = launch_blend((const float4 *)splats->rec, bins->values, bins->ranges, ck, bg, img, final_T,
-                                      n_contrib, (hipStream_t)stream, e0, e1);
+    const hipError_t e = launch_blend((const float4 *)splats->rec, bins->values, bins->ranges, bins->order, ck, bg,
+                                      img, final_T, n_contrib, (hipStream_t)stream, e0, e1);
     return hip_status(e, "d4dgs_render_fwd");
 }
 
@@ -290,7 +290,8 @@ d4dgs_status render_bwd_impl(const d4dgs_scene *scene, const d4dgs_camera *cam, 
         return fail(D4DGS_ERR_INVALID_ARG, "render_bwd: splitting statistics must be all set or all NULL");
     const SceneK sk = make_scenek(*scene);
     const CamK ck = make_camk(*cam);
-    hipError_t e = launch_blend_bwd((const float4 *)splats->rec, splats->offset, bins->values, bins->ranges, ck, bg,
+    hipError_t e = launch_blend_bwd((const float4 *)splats->rec, splats->offset, bins->values, bins->ranges,
+                                    bins->order, ck, bg,
                                     final_T, n_contrib, dL_dimg, dL_dflow ? (const float2 *)splats->mdot : nullptr,
                                     dL_dflow, (float4 *)inst_grads, bins->capacity, (hipStream_t)stream);
     if (e == hipSuccess)
@@ -339,7 +340,8 @@ d4dgs_status d4dgs_render_fwd_flow(const d4dgs_splats *splats, const d4dgs_bins 
     dummy.height = height;
     const CamK ck = make_camk(dummy);
     const hipError_t e = launch_blend_flow((const float4 *)splats->rec, (const float2 *)splats->mdot, bins->values,
-                                           bins->ranges, ck, bg, img, flow, final_T, n_contrib, (hipStream_t)stream);
+                                           bins->ranges, bins->order, ck, bg, img, flow, final_T, n_contrib,
+                                           (hipStream_t)stream);
     return hip_status(e, "d4dgs_render_fwd_flow");
 }
 
@@ -468,10 +470,10 @@ d4dgs_status d4dgs_render_times(const d4dgs_scene *scene, const d4dgs_camera *ca
         const SortWs ws = carve_workspace(workspace[i], scene->n, bins[i].capacity, tiles);
         e = launch_bin_sort((const float4 *)splats[i].rec, splats[i].count, splats[i].offset, splats[i].partial,
                             scene->n, ck, ws, bins[i].keys, bins[i].values, bins[i].ranges, bins[i].num_instances,
-                            bins[i].capacity, d_status, fs);
+                            bins[i].capacity, d_status, bins[i].order, fs);
         if (e == hipSuccess)
-            e = launch_blend((const float4 *)splats[i].rec, bins[i].values, bins[i].ranges, ck, bg, img[i], nullptr,
-                             nullptr, fs);
+            e = launch_blend((const float4 *)splats[i].rec, bins[i].values, bins[i].ranges, bins[i].order, ck, bg,
+                             img[i], nullptr, nullptr, fs);
     }
     // join (also after a failed launch, so that the caller's stream never runs ahead)
     for (int k = 0; k < S; ++k) {

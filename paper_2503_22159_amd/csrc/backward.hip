@@ -123,17 +123,16 @@ template <bool FLOW>
 __global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restrict__ rec,
                                                            const uint32_t *__restrict__ offset,
                                                            const uint32_t *__restrict__ vals,
-                                                           const uint32_t *__restrict__ ranges, CamK c, float bg0,
+                                                           const uint32_t *__restrict__ ranges,
+                                                           const uint32_t *__restrict__ order, CamK c, float bg0,
                                                            float bg1, float bg2, const float *__restrict__ final_T,
                                                            const uint32_t *__restrict__ ncontrib,
                                                            const float *__restrict__ dL, float4 *__restrict__ ig,
-                                                           uint32_t capacity, int ntiles, int per_xcd,
-                                                           const float2 *__restrict__ mdot,
+                                                           uint32_t capacity, const float2 *__restrict__ mdot,
                                                            const float *__restrict__ dLf) {
     constexpr int NR = FLOW ? 11 : 9;  // sums reduced per splat
-    const int b = blockIdx.x;
-    const int tile = (b & 7) * per_xcd + (b >> 3);
-    if (tile >= ntiles) return;
+    int tile, unused;
+    if (!tile_unit(blockIdx.x, c.TX, c.TY, 1, order, tile, unused)) return;  // the same for the whole workgroup
     const int tx = tile % c.TX, ty = tile / c.TX;
     const int tid = threadIdx.x, w = tid / kWave, ln = lane_id();
     const size_t plane = (size_t)c.W * c.H;
@@ -581,20 +580,19 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
 }  // namespace
 
 hipError_t launch_blend_bwd(const float4 *rec, const uint32_t *offset, const uint32_t *vals, const uint32_t *ranges,
-                            const CamK &c, const float bg[3], const float *final_T, const uint32_t *n_contrib,
+                            const uint32_t *order, const CamK &c, const float bg[3], const float *final_T, const uint32_t *n_contrib,
                             const float *dL_dimg, const float2 *mdot, const float *dL_dflow, float4 *inst_grads,
                             int64_t capacity, hipStream_t st) {
     const int ntiles = c.TX * c.TY;
     if (ntiles == 0) return hipSuccess;
-    const int per_xcd = (ntiles + 7) / 8;
+    const dim3 grid(tile_grid(c.TX, c.TY, 1));
     if (mdot && dL_dflow)
-        hipLaunchKernelGGL(k_blend_bwd<true>, dim3(per_xcd * 8), dim3(kBwdThreads), 0, st, rec, offset, vals, ranges, c,
-                           bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, ntiles,
-                           per_xcd, mdot, dL_dflow);
+        hipLaunchKernelGGL(k_blend_bwd<true>, grid, dim3(kBwdThreads), 0, st, rec, offset, vals, ranges, order, c, bg[0],
+                           bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, mdot, dL_dflow);
     else
-        hipLaunchKernelGGL(k_blend_bwd<false>, dim3(per_xcd * 8), dim3(kBwdThreads), 0, st, rec, offset, vals, ranges, c,
-                           bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, ntiles,
-                           per_xcd, nullptr, nullptr);
+        hipLaunchKernelGGL(k_blend_bwd<false>, grid, dim3(kBwdThreads), 0, st, rec, offset, vals, ranges, order, c, bg[0],
+                           bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, nullptr,
+                           nullptr);
     return hipGetLastError();
 }
 

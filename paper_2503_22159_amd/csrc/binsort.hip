@@ -13,6 +13,8 @@
 //                    owner found by binary search over the wave prefix), so splats with
 //                    large rectangles do not stall a wave.
 //   k_tile_scan      one block: exclusive scan over tiles -> ranges, bucket cursors.
+//                    (With a tile order, the scatter pass has one more workgroup, which
+//                    sorts the tiles by list length for the launches that follow.)
 //   k_tile_sort      one workgroup of 256 per tile sorts its bucket by the 64-bit key --
 //                    depth, ties by Gaussian index: a unique order, so the result does not
 //                    depend on the order the atomics handed out positions.  Buckets of up to
@@ -105,22 +107,91 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t *__rest
 //   atomics.
 constexpr int kCells = 2048;
 
+// Tile order of the per-tile launches (see tile_unit): the tiles of row class x (rows
+// x, x + 8, ...: the tiles XCD x takes) form the x-th segment of the order, and inside a
+// segment the tiles are ordered by list length, longest first, in steps of 8 (lists of
+// 2,040 or more share the first step).  Work on a tile (its sort, its blend, its
+// adjoint) grows with its list, so each XCD starts with its long lists and they do not
+// run alone at the end of a launch.  One extra workgroup of the scatter pass builds it
+// (a counting sort in LDS), next to the scatter and off the frame's critical path.
+constexpr int kOrderShift = 3;
+constexpr int kOrderKeys = 8 * kRadix;  // row class x 256 length steps
+__device__ __forceinline__ uint32_t order_key(int tile, int TX, uint32_t count) {
+    return (uint32_t)((tile / TX) & 7) * kRadix + (255u - min(count >> kOrderShift, 255u));
+}
+
+// hist: kOrderKeys words of LDS; 256 threads
+__device__ void build_tile_order(const uint32_t *__restrict__ ranges, int tiles, int TX, uint32_t *__restrict__ order,
+                                 uint32_t *hist, uint32_t *tmp4) {
+    constexpr int KPT = kOrderKeys / kBlock;  // keys per thread in the scan
+    const int tid = threadIdx.x;
+    for (int k = tid; k < kOrderKeys; k += kBlock) hist[k] = 0u;
+    __syncthreads();
+    for (int i0 = tid; i0 < tiles; i0 += 4 * kBlock) {
+        uint2 r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = i0 + u * kBlock < tiles ? make_uint2(ranges[2 * (i0 + u * kBlock)], ranges[2 * (i0 + u * kBlock) + 1])
+                                              : make_uint2(0u, 0u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * kBlock < tiles) atomicAdd(&hist[order_key(i0 + u * kBlock, TX, r[u].y - r[u].x)], 1u);
+    }
+    __syncthreads();
+    uint32_t v[KPT], sum = 0;
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        v[j] = hist[KPT * tid + j];
+        sum += v[j];
+    }
+    uint32_t base = block_excl_scan_256(sum, tmp4);
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        hist[KPT * tid + j] = base;
+        base += v[j];
+    }
+    __syncthreads();
+    // the order inside a key is whatever the LDS atomics give: it only decides when a
+    // tile is processed, never a result
+    for (int i0 = tid; i0 < tiles; i0 += 4 * kBlock) {
+        uint2 r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = i0 + u * kBlock < tiles ? make_uint2(ranges[2 * (i0 + u * kBlock)], ranges[2 * (i0 + u * kBlock) + 1])
+                                              : make_uint2(0u, 0u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * kBlock;
+            if (i < tiles) order[atomicAdd(&hist[order_key(i, TX, r[u].y - r[u].x)], 1u)] = (uint32_t)i;
+        }
+    }
+}
+
+
 template <bool RESERVE>
 __global__ __launch_bounds__(kBlock) void k_emit(const float4 *__restrict__ rec, const uint32_t *__restrict__ count,
                                                  const uint32_t *__restrict__ partial, uint32_t *__restrict__ offset,
                                                  int n, int TX, const uint32_t *__restrict__ misc,
                                                  uint32_t *__restrict__ tcnt, uint32_t *__restrict__ grp_off,
-                                                 uint32_t *__restrict__ inst_off, uint64_t *__restrict__ bucket) {
-    if (misc[1] != 0u) return;  // capacity exceeded: nothing downstream runs
+                                                 uint32_t *__restrict__ inst_off, uint64_t *__restrict__ bucket,
+                                                 const uint32_t *__restrict__ ranges, int tiles,
+                                                 uint32_t *__restrict__ order) {
+    static_assert(kCells >= kOrderKeys, "the tile order's histogram lives in s_cell");
     __shared__ uint32_t tmp4[kBlock / kWave];
     __shared__ uint32_t s_incl[kBlock];
     __shared__ uint32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock], s_dbits[kBlock];
     __shared__ uint32_t s_cell[kCells];
     __shared__ uint32_t s_box[4][kBlock / kWave];
-    const int tid = threadIdx.x, gi = blockIdx.x * kBlock + tid, wv = tid / kWave;
+    // with a tile order the scatter pass has one extra workgroup, the first one (so that
+    // it starts first), which builds the order (also on overflow: the blends read it)
+    const int blk = (int)blockIdx.x - ((!RESERVE && order) ? 1 : 0);
+    if (blk < 0) {
+        build_tile_order(ranges, tiles, TX, order, s_cell, tmp4);
+        return;
+    }
+    if (misc[1] != 0u) return;  // capacity exceeded: nothing downstream runs
+    const int tid = threadIdx.x, gi = blk * kBlock + tid, wv = tid / kWave;
     const uint32_t cnt = gi < n ? count[gi] : 0u;
     const uint32_t excl = block_excl_scan_256(cnt, tmp4);
-    const uint32_t boff = partial[blockIdx.x];
+    const uint32_t boff = partial[blk];
     if (RESERVE && gi < n) offset[gi] = boff + excl;
     s_incl[tid] = wave_incl_scan(cnt);
     uint32_t bx0 = 0xffffu, by0 = 0xffffu, bx1 = 0u, by1 = 0u;
@@ -186,10 +257,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4 *__restrict__ rec,
         } else {
             uint32_t pos;
             if (grouped)
-                pos = tcnt[tile] + grp_off[(size_t)blockIdx.x * kCells + cell] + atomicAdd(&s_cell[cell], 1u);
+                pos = tcnt[tile] + grp_off[(size_t)blk * kCells + cell] + atomicAdd(&s_cell[cell], 1u);
             else
                 pos = tcnt[tile] + inst_off[wstart + j];
-            bucket[pos] = ((uint64_t)s_dbits[o] << 32) | (uint32_t)(blockIdx.x * kBlock + o);
+            bucket[pos] = ((uint64_t)s_dbits[o] << 32) | (uint32_t)(blk * kBlock + o);
         }
     }
     if (RESERVE && grouped) {
@@ -198,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4 *__restrict__ rec,
             const uint32_t k = s_cell[c];
             if (k) {
                 const uint32_t tile = (by0 + c / uw) * (uint32_t)TX + (bx0 + c % uw);
-                grp_off[(size_t)blockIdx.x * kCells + c] = atomicAdd(&tcnt[tile], k);
+                grp_off[(size_t)blk * kCells + c] = atomicAdd(&tcnt[tile], k);
             }
         }
     }
@@ -318,13 +389,14 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint64_t *__re
                                                             const uint32_t *__restrict__ ranges, int tiles,
                                                             uint64_t *__restrict__ keys,
                                                             uint32_t *__restrict__ vals,
-                                                            const uint32_t *__restrict__ misc) {
+                                                            const uint32_t *__restrict__ misc,
+                                                            const uint32_t *__restrict__ order, int TX, int TY) {
     if (misc[1] != 0u) return;
     __shared__ uint32_t cnt[kRadix];
     __shared__ uint32_t wc[(kSortThreads / kWave) * kRadix];
     __shared__ uint32_t tmp4[kSortThreads / kWave];
-    const int tile = blockIdx.x;
-    if (tile >= tiles) return;
+    int tile, unused;
+    if (!tile_unit(blockIdx.x, TX, TY, 1, order, tile, unused)) return;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     const uint32_t s = end - start;
     const uint32_t tid = threadIdx.x;
@@ -384,20 +456,25 @@ SortWs carve_workspace(void *ws, int n, int64_t capacity, int tiles) {
 
 hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *offset, uint32_t *partial, int n,
                            const CamK &c, const SortWs &ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
-                           int64_t *num_inst, int64_t capacity, int32_t *d_status, hipStream_t st) {
+                           int64_t *num_inst, int64_t capacity, int32_t *d_status, uint32_t *order,
+                           hipStream_t st) {
     const int tiles = c.TX * c.TY;
     const int nb = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partial, nb, capacity, num_inst,
                        ws.misc, d_status, ws.tcnt, tiles);
     if (nb > 0)
         hipLaunchKernelGGL(k_emit<true>, dim3(nb), dim3(kBlock), 0, st, rec, count, partial, offset, n, c.TX,
-                           ws.misc, ws.tcnt, ws.grp_off, ws.inst_off, ws.bucket);
+                           ws.misc, ws.tcnt, ws.grp_off, ws.inst_off, ws.bucket, (const uint32_t *)nullptr, tiles,
+                           (uint32_t *)nullptr);
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanThreads), 0, st, ws.tcnt, tiles, ranges, ws.misc);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_emit<false>, dim3(nb), dim3(kBlock), 0, st, rec, count, partial, offset, n, c.TX,
-                           ws.misc, ws.tcnt, ws.grp_off, ws.inst_off, ws.bucket);
-    hipLaunchKernelGGL(k_tile_sort, dim3(tiles), dim3(kSortThreads), 0, st, (const uint64_t *)ws.bucket, ws.alt, ranges, tiles, keys, vals,
-                       ws.misc);
+    // scatter; with a tile order one more workgroup (the first) builds it
+    if (nb > 0 || order)
+        hipLaunchKernelGGL(k_emit<false>, dim3(nb + (order ? 1 : 0)), dim3(kBlock), 0, st, rec, count, partial,
+                           offset, n, c.TX, ws.misc, ws.tcnt, ws.grp_off, ws.inst_off, ws.bucket,
+                           (const uint32_t *)ranges, tiles, order);
+    hipLaunchKernelGGL(k_tile_sort, dim3(tile_grid(c.TX, c.TY, 1)), dim3(kSortThreads), 0, st,
+                       (const uint64_t *)ws.bucket, ws.alt, ranges, tiles, keys, vals, ws.misc,
+                       (const uint32_t *)order, c.TX, c.TY);
     return hipGetLastError();
 }
 

@@ -9,9 +9,8 @@
 // terms of the exponent that depend only on the column are formed once per lane and
 // shared by its pixels.  A wave stops as soon as all of its pixels are saturated.
 //
-// Launch order is XCD-aware: the hardware deals consecutive workgroups round-robin to the
-// 8 XCDs, so block b takes logical block (b % 8) * per_xcd + b / 8 -- each XCD renders a
-// contiguous band of tiles, and neighbouring tiles, which share splats, share its L2.
+// Launch order (tile_unit): the binning's longest-first tile order dealt round-robin over
+// the XCDs, or, without it, every eighth row of tiles per XCD.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -70,9 +69,10 @@ __device__ __forceinline__ bool blend_splat(const float4 &g0, const float4 &g1, 
 
 template <int PX, int RW, bool STATE, bool FLOW>
 __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
-                                                 const uint32_t *__restrict__ ranges, CamK c, float bg0, float bg1,
+                                                 const uint32_t *__restrict__ ranges,
+                                                 const uint32_t *__restrict__ order, CamK c, float bg0, float bg1,
                                                  float bg2, float *__restrict__ img, float *__restrict__ final_T,
-                                                 uint32_t *__restrict__ ncontrib, int nlogical, int per_xcd,
+                                                 uint32_t *__restrict__ ncontrib,
                                                  const float2 *__restrict__ mdot, float *__restrict__ flow) {
     constexpr int LR = kWave / RW;      // lane rows
     constexpr int RH = LR * PX;         // rows of the wavefront's pixel region (RW x RH)
@@ -82,10 +82,8 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
     // s2[i] = {b, bits(plain << 31 | list position + 1), mdot.x, mdot.y}: strided like s0
     // and s1 so that one address register serves all three reads
     __shared__ float4 s0[kWave], s1[kWave], s2[kWave];
-    const int b = blockIdx.x;
-    const int L = (b & 7) * per_xcd + (b >> 3);
-    if (L >= nlogical) return;
-    const int tile = L / WPT, sub = L % WPT;
+    int tile, sub;
+    if (!tile_unit(blockIdx.x, c.TX, c.TY, WPT, order, tile, sub)) return;
     const int tx = tile % c.TX, ty = tile / c.TX;
     const int rx0 = tx * kTile + (sub % NXR) * RW, ry0 = ty * kTile + (sub / NXR) * RH;
     const int ln = lane_id();
@@ -196,27 +194,26 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
 // With events e0/e1 the launch goes through hipExtLaunchKernel, which sets them to the
 // kernel's own start and end (a stream-ordered event pair would also time the dispatch).
 template <int PX, int RW>
-void launch_px(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c, const float bg[3],
+void launch_px(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const uint32_t *order, const CamK &c,
+               const float bg[3],
                float *img, float *final_T, uint32_t *n_contrib, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    const int nlogical = c.TX * c.TY * (4 / PX);
-    const int per_xcd = (nlogical + 7) / 8;
-    const dim3 grid(per_xcd * 8), block(kWave);
+    const dim3 grid(tile_grid(c.TX, c.TY, 4 / PX)), block(kWave);
     if (final_T) {
         if (e0)
-            hipExtLaunchKernelGGL((k_blend<PX, RW, true, false>), grid, block, 0, st, e0, e1, 0, rec, vals, ranges, c,
-                                  bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd,
+            hipExtLaunchKernelGGL((k_blend<PX, RW, true, false>), grid, block, 0, st, e0, e1, 0, rec, vals, ranges, order, c,
+                                  bg[0], bg[1], bg[2], img, final_T, n_contrib,
                                   (const float2 *)nullptr, (float *)nullptr);
         else
-            hipLaunchKernelGGL((k_blend<PX, RW, true, false>), grid, block, 0, st, rec, vals, ranges, c, bg[0], bg[1],
-                               bg[2], img, final_T, n_contrib, nlogical, per_xcd, nullptr, nullptr);
+            hipLaunchKernelGGL((k_blend<PX, RW, true, false>), grid, block, 0, st, rec, vals, ranges, order, c, bg[0], bg[1],
+                               bg[2], img, final_T, n_contrib, nullptr, nullptr);
     } else {
         if (e0)
-            hipExtLaunchKernelGGL((k_blend<PX, RW, false, false>), grid, block, 0, st, e0, e1, 0, rec, vals, ranges, c,
-                                  bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd,
+            hipExtLaunchKernelGGL((k_blend<PX, RW, false, false>), grid, block, 0, st, e0, e1, 0, rec, vals, ranges, order, c,
+                                  bg[0], bg[1], bg[2], img, final_T, n_contrib,
                                   (const float2 *)nullptr, (float *)nullptr);
         else
-            hipLaunchKernelGGL((k_blend<PX, RW, false, false>), grid, block, 0, st, rec, vals, ranges, c, bg[0], bg[1],
-                               bg[2], img, final_T, n_contrib, nlogical, per_xcd, nullptr, nullptr);
+            hipLaunchKernelGGL((k_blend<PX, RW, false, false>), grid, block, 0, st, rec, vals, ranges, order, c, bg[0], bg[1],
+                               bg[2], img, final_T, n_contrib, nullptr, nullptr);
     }
 }
 
@@ -235,32 +232,31 @@ int blend_variant() {
 
 }  // namespace
 
-hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c,
-                        const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st,
-                        hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const uint32_t *order,
+                        const CamK &c, const float bg[3], float *img, float *final_T, uint32_t *n_contrib,
+                        hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (c.TX * c.TY == 0) return hipSuccess;
     switch (blend_variant()) {
-        case 116: launch_px<1, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st, e0, e1); break;
-        case 208: launch_px<2, 8>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st, e0, e1); break;
-        case 216: launch_px<2, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st, e0, e1); break;
-        case 416: launch_px<4, 16>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st, e0, e1); break;
-        default: launch_px<1, 8>(rec, vals, ranges, c, bg, img, final_T, n_contrib, st, e0, e1); break;
+        case 116: launch_px<1, 16>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1); break;
+        case 208: launch_px<2, 8>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1); break;
+        case 216: launch_px<2, 16>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1); break;
+        case 416: launch_px<4, 16>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1); break;
+        default: launch_px<1, 8>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_blend_flow(const float4 *rec, const float2 *mdot, const uint32_t *vals, const uint32_t *ranges,
-                             const CamK &c, const float bg[3], float *img, float *flow, float *final_T,
+                             const uint32_t *order, const CamK &c, const float bg[3], float *img, float *flow, float *final_T,
                              uint32_t *n_contrib, hipStream_t st) {
     if (c.TX * c.TY == 0) return hipSuccess;
-    const int nlogical = c.TX * c.TY * 4;  // one pixel per lane, 8x8 squares
-    const int per_xcd = (nlogical + 7) / 8;
+    const dim3 grid(tile_grid(c.TX, c.TY, 4));  // one pixel per lane, 8x8 squares
     if (final_T)
-        hipLaunchKernelGGL((k_blend<1, 8, true, true>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges, c,
-                           bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd, mdot, flow);
+        hipLaunchKernelGGL((k_blend<1, 8, true, true>), grid, dim3(kWave), 0, st, rec, vals, ranges, order, c,
+                           bg[0], bg[1], bg[2], img, final_T, n_contrib, mdot, flow);
     else
-        hipLaunchKernelGGL((k_blend<1, 8, false, true>), dim3(per_xcd * 8), dim3(kWave), 0, st, rec, vals, ranges,
-                           c, bg[0], bg[1], bg[2], img, final_T, n_contrib, nlogical, per_xcd, mdot, flow);
+        hipLaunchKernelGGL((k_blend<1, 8, false, true>), grid, dim3(kWave), 0, st, rec, vals, ranges,
+                           order, c, bg[0], bg[1], bg[2], img, final_T, n_contrib, mdot, flow);
     return hipGetLastError();
 }
 

@@ -143,6 +143,38 @@ __device__ __forceinline__ float pix_exponent(const ColTerms &t, const float4 &f
     return __builtin_fmaf(__builtin_fmaf(f1.x, dy, t.B0), dy, t.A0);
 }
 
+// --- tile order of the per-tile launches ---------------------------------------------
+// The hardware deals a launch's workgroups round-robin to the 8 XCDs: block b runs on
+// XCD b % 8, as the k-th (k = b / 8) workgroup that XCD receives.  A launch does upt
+// units of work per tile (a unit being one workgroup); a tile's units run consecutively
+// on one XCD and share its L2.  XCD x takes the tiles of rows x, x + 8, x + 16, ...: that
+// spreads the scene's dense middle evenly (a contiguous band per XCD left the XCDs under
+// it with twice the work of the others) and keeps the tiles an XCD renders, and the
+// splats they share, within its L2.  Without a tile order an XCD takes its tiles row by
+// row; with one (written by the binning: segment x holds XCD x's tiles, longest list
+// first) it starts with its long lists, so that they do not run alone at the end.
+__host__ __device__ inline int tile_grid(int TX, int TY, int upt) { return 8 * ((TY + 7) / 8) * TX * upt; }
+
+__device__ __forceinline__ int class_rows(int TY, int x) { return TY > x ? (TY - 1 - x) / 8 + 1 : 0; }
+
+__device__ __forceinline__ bool tile_unit(int b, int TX, int TY, int upt, const uint32_t *__restrict__ order,
+                                          int &tile, int &sub) {
+    const int x = b & 7, k = b >> 3;
+    const int j = k / upt;  // the XCD's j-th tile
+    sub = k - j * upt;
+    if (j >= TX * class_rows(TY, x)) return false;
+    if (order) {
+        int off = 0;
+        for (int y = 0; y < x; ++y) off += class_rows(TY, y);
+        const uint32_t o = order[TX * off + j];
+        if (o >= (uint32_t)(TX * TY)) return false;  // an order not written by the binning stays in bounds
+        tile = (int)o;
+    } else {
+        tile = (x + 8 * (j / TX)) * TX + j % TX;
+    }
+    return true;
+}
+
 // --- launchers (host side) ----------------------------------------------------------
 struct SceneK {
     int n, deg;
@@ -200,22 +232,25 @@ struct SortWs {
 size_t sort_workspace_bytes(int n, int64_t capacity, int tiles);
 SortWs carve_workspace(void *ws, int n, int64_t capacity, int tiles);
 
+// order (optional, [tiles]): receives the tiles longest list first
 hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *offset, uint32_t *partial, int n,
                            const CamK &c, const SortWs &ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
-                           int64_t *num_inst, int64_t capacity, int32_t *d_status, hipStream_t st);
+                           int64_t *num_inst, int64_t capacity, int32_t *d_status, uint32_t *order,
+                           hipStream_t st);
 
-// e0/e1 (optional): events set to the blend kernel's own start and end
-hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const CamK &c,
-                        const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st,
-                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// order (optional): the binning's tile order; e0/e1 (optional): events set to the blend
+// kernel's own start and end
+hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const uint32_t *order,
+                        const CamK &c, const float bg[3], float *img, float *final_T, uint32_t *n_contrib,
+                        hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // the blend with the optical flow: mdot [n] per splat, flow [2][H][W]
 hipError_t launch_blend_flow(const float4 *rec, const float2 *mdot, const uint32_t *vals, const uint32_t *ranges,
-                             const CamK &c, const float bg[3], float *img, float *flow, float *final_T,
+                             const uint32_t *order, const CamK &c, const float bg[3], float *img, float *flow, float *final_T,
                              uint32_t *n_contrib, hipStream_t st);
 
 // mdot / dL_dflow NULL: colour only
 hipError_t launch_blend_bwd(const float4 *rec, const uint32_t *offset, const uint32_t *vals,
-                            const uint32_t *ranges, const CamK &c, const float bg[3], const float *final_T,
+                            const uint32_t *ranges, const uint32_t *order, const CamK &c, const float bg[3], const float *final_T,
                             const uint32_t *n_contrib, const float *dL_dimg, const float2 *mdot,
                             const float *dL_dflow, float4 *inst_grads, int64_t capacity, hipStream_t st);
 

@@ -101,7 +101,7 @@ struct Req {
 };
 
 struct Layout {
-    size_t rec, count, offset, partial, keys, vals, ranges, ninst, ws, total;
+    size_t rec, count, offset, partial, keys, vals, ranges, order, ninst, ws, total;
     size_t ws_bytes;
 };
 
@@ -117,6 +117,7 @@ Layout layout(int n, int W, int H, int64_t cap) {
     L.keys = p; p += al((size_t)cap * 8);
     L.vals = p; p += al((size_t)cap * 4);
     L.ranges = p; p += al((size_t)tiles * 8);
+    L.order = p; p += al((size_t)tiles * 4);
     L.ninst = p; p += al(16);
     L.ws_bytes = sort_workspace_bytes(n, cap, tiles);
     L.ws = p; p += al(L.ws_bytes);
@@ -207,10 +208,11 @@ void d4dgs_server::launch(Batch &b) {
         e = launch_bin_sort((const float4 *)(base + L.rec), (const uint32_t *)(base + L.count),
                             (uint32_t *)(base + L.offset), (uint32_t *)(base + L.partial), scene.n, ck, ws,
                             (uint64_t *)(base + L.keys), (uint32_t *)(base + L.vals), (uint32_t *)(base + L.ranges),
-                            (int64_t *)(base + L.ninst), r->capacity, nullptr, st);
+                            (int64_t *)(base + L.ninst), r->capacity, nullptr, (uint32_t *)(base + L.order), st);
         if (e == hipSuccess)
             e = launch_blend((const float4 *)(base + L.rec), (const uint32_t *)(base + L.vals),
-                             (const uint32_t *)(base + L.ranges), ck, cfg.bg, r->out, nullptr, nullptr, st);
+                             (const uint32_t *)(base + L.ranges), (const uint32_t *)(base + L.order), ck, cfg.bg,
+                             r->out, nullptr, nullptr, st);
         if (e == hipSuccess)  // instance total and overflow status back to pinned memory
             e = hipMemcpyAsync(pinned + 2 * r->slot, base + L.ninst, 8, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)

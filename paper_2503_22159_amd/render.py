@@ -66,7 +66,7 @@ class DeviceScene:
 class FrameState:
     """Device buffers of one rendered frame (splat record, sorted bins, replay state)."""
 
-    def __init__(self, n, width, height, capacity, device="cuda", flow=False, motion=0):
+    def __init__(self, n, width, height, capacity, device="cuda", flow=False, motion=0, tile_order=True):
         self.n, self.width, self.height, self.capacity = n, width, height, int(capacity)
         self.motion = int(motion)  # d4dgs_motion of the time stage
         dev = device
@@ -78,6 +78,8 @@ class FrameState:
         self.keys = torch.empty(self.capacity, dtype=torch.int64, device=dev)
         self.values = torch.empty(self.capacity, dtype=torch.int32, device=dev)
         self.ranges = torch.empty(2 * tiles_of(width, height), dtype=torch.int32, device=dev)
+        # tiles longest list first, written by the binning (scheduling of the per-tile kernels)
+        self.order = torch.empty(max(tiles_of(width, height), 1), dtype=torch.int32, device=dev) if tile_order else None
         self.num_inst = torch.zeros(1, dtype=torch.int64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.ws = torch.empty(B.workspace_size(n, width, height, self.capacity), dtype=torch.uint8, device=dev)
@@ -103,6 +105,7 @@ class FrameState:
         b.capacity = self.capacity
         b.keys, b.values, b.ranges, b.num_instances = (self.keys.data_ptr(), self.values.data_ptr(),
                                                        self.ranges.data_ptr(), self.num_inst.data_ptr())
+        b.order = self.order.data_ptr() if self.order is not None else None
         return b
 
 
@@ -341,12 +344,13 @@ class Renderer:
     object: cameras passed here are treated as immutable), so a frame costs three
     foreign calls on the host."""
 
-    def __init__(self, scene: DeviceScene, width, height, capacity=None, cache=True, keep_state=False):
+    def __init__(self, scene: DeviceScene, width, height, capacity=None, cache=True, keep_state=False,
+                 tile_order=True):
         self.scene = scene
         self.width, self.height = int(width), int(height)
         dev = scene.t["mean"].device
         self.st = FrameState(scene.n, self.width, self.height,
-                             capacity or default_capacity(scene.n, width, height), dev)
+                             capacity or default_capacity(scene.n, width, height), dev, tile_order=tile_order)
         self.cache = CamCache(scene.n, dev) if cache else None
         self.keep_state = keep_state
         self.img = torch.empty((3, self.height, self.width), dtype=torch.float32, device=dev)

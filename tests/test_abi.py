@@ -38,7 +38,7 @@ def test_binding_structs_match_header_sizes():
     assert C.sizeof(B.Camera) == 4 * 2 + 4 * 7 + 4 * 9 + 4 * 3 + 4 * 3
     assert C.sizeof(B.Scene) == 8 + 8 * 8
     assert C.sizeof(B.Splats) == 8 + 8 * 5 + 8  # capacity (padded), 5 pointers, motion (padded)
-    assert C.sizeof(B.Bins) == 8 + 8 * 4
+    assert C.sizeof(B.Bins) == 8 + 8 * 5
     assert B.lib.d4dgs_abi_version() == B.ABI_VERSION
     assert set(B.EXPORTS) == set(declared_functions())
 

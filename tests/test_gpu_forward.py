@@ -229,3 +229,41 @@ def test_timed_blend_matches_and_times_the_kernel(R):
                                      C.byref(rend._bg((0.0, 0.0, 0.0))), rend._img, None, None, None, None,
                                      R._stream())
     assert r == B.ERR_INVALID_ARG and "event" in B.last_error()
+
+
+def test_tile_order_is_longest_first_and_changes_nothing(R):
+    """With a tile order the binning lists the tiles grouped by row mod 8 and, inside a
+    group, longest list first (lengths in steps of 8); the per-tile kernels run in that
+    order.  The sorted lists, the image, the replay state and the gradients are bitwise
+    those of the row-order launch."""
+    import torch
+
+    sc = inputs.config2_scene(n=40_000)
+    cam = inputs.arc_camera(7, width=337, height=253)
+    t = np.float32(0.5)
+    ds = R.DeviceScene.from_inputs(sc)
+    dL = torch.from_numpy(inputs.upstream_grad(5, cam.width, cam.height)).cuda()
+    outs = []
+    for use_order in (True, False):
+        st = R.FrameState(sc.n, cam.width, cam.height, 400_000, tile_order=use_order)
+        R.project(ds, cam, t, st)
+        R.bin_sort(st)
+        img = R.blend(st, (0.1, 0.2, 0.3), keep_state=True)
+        g = R.render_backward(ds, cam, t, (0.1, 0.2, 0.3), st, dL)
+        torch.cuda.synchronize()
+        outs.append(([img.cpu().numpy(), st.final_T.cpu().numpy(), st.n_contrib.cpu().numpy()]
+                     + [g[k].cpu().numpy() for k in sorted(g)], read_bins(st),
+                     st.order.cpu().numpy().view(np.uint32) if use_order else None))
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(a, b)
+    assert_bins_equal(outs[0][1], outs[1][1])
+    order, bins = outs[0][2], outs[0][1]
+    tiles = bins["ranges"].shape[0]
+    assert np.array_equal(np.sort(order), np.arange(tiles))
+    cnt = bins["ranges"][:, 1].astype(np.int64) - bins["ranges"][:, 0]
+    TX = (cam.width + 15) // 16
+    cls = (order // TX) % 8
+    assert np.all(np.diff(cls) >= 0)
+    for x in range(8):
+        seg = order[cls == x]
+        assert np.all(np.diff(np.minimum(cnt[seg] >> 3, 255)) <= 0)
