@@ -371,7 +371,7 @@ d4dgs_status d4dgs_flow_loss(const float *img, const float *flow, int32_t width,
 // Streams and events of d4dgs_render_times, one set per device, created on first use
 // and kept until the process ends.
 struct TimesPool {
-    static constexpr int kStreams = 3;
+    static constexpr int kStreams = 4;
     std::mutex mu;
     bool ready = false;
     hipStream_t s[kStreams] = {};

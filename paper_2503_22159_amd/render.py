@@ -429,12 +429,13 @@ class TimesRenderer:
     d4dgs_render_times call (camera stage once, batched time stages, per-frame binning
     and blending on the library's own streams)."""
 
-    def __init__(self, scene: DeviceScene, width, height, T, capacity=None, cache=True):
+    def __init__(self, scene: DeviceScene, width, height, T, capacity=None, cache=True, tile_order=True):
         self.scene = scene
         self.width, self.height, self.T = int(width), int(height), int(T)
         dev = scene.t["mean"].device
         cap = capacity or default_capacity(scene.n, width, height)
-        self.frames = [FrameState(scene.n, self.width, self.height, cap, dev) for _ in range(self.T)]
+        self.frames = [FrameState(scene.n, self.width, self.height, cap, dev, tile_order=tile_order)
+                       for _ in range(self.T)]
         self.imgs = [torch.empty((3, self.height, self.width), dtype=torch.float32, device=dev) for _ in range(self.T)]
         self.cache = CamCache(scene.n, dev) if cache else None
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
