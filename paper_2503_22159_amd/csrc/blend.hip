@@ -9,11 +9,8 @@
 // terms of the exponent that depend only on the column are formed once per lane and
 // shared by its pixels.  A wave stops as soon as all of its pixels are saturated.
 //
-// Launch order (tile_unit): the binning's longest-first tile order dealt round-robin over
-// the XCDs, or, without it, every eighth row of tiles per XCD.
-#include <stdio.h>
-#include <stdlib.h>
-
+// Launch order (tile_unit): XCD x takes every eighth row of tiles from row x, in the
+// binning's longest-first order when it is given.
 #include <hip/hip_ext.h>
 
 #include "internal.hpp"
@@ -193,41 +190,19 @@ __global__ __launch_bounds__(kWave) void k_blend(const float4 *__restrict__ rec,
 
 // With events e0/e1 the launch goes through hipExtLaunchKernel, which sets them to the
 // kernel's own start and end (a stream-ordered event pair would also time the dispatch).
-template <int PX, int RW>
+template <int PX, int RW, bool STATE>
 void launch_px(const float4 *rec, const uint32_t *vals, const uint32_t *ranges, const uint32_t *order, const CamK &c,
-               const float bg[3],
-               float *img, float *final_T, uint32_t *n_contrib, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+               const float bg[3], float *img, float *final_T, uint32_t *n_contrib, hipStream_t st, hipEvent_t e0,
+               hipEvent_t e1) {
     const dim3 grid(tile_grid(c.TX, c.TY, 4 / PX)), block(kWave);
-    if (final_T) {
-        if (e0)
-            hipExtLaunchKernelGGL((k_blend<PX, RW, true, false>), grid, block, 0, st, e0, e1, 0, rec, vals, ranges, order, c,
-                                  bg[0], bg[1], bg[2], img, final_T, n_contrib,
-                                  (const float2 *)nullptr, (float *)nullptr);
-        else
-            hipLaunchKernelGGL((k_blend<PX, RW, true, false>), grid, block, 0, st, rec, vals, ranges, order, c, bg[0], bg[1],
-                               bg[2], img, final_T, n_contrib, nullptr, nullptr);
-    } else {
-        if (e0)
-            hipExtLaunchKernelGGL((k_blend<PX, RW, false, false>), grid, block, 0, st, e0, e1, 0, rec, vals, ranges, order, c,
-                                  bg[0], bg[1], bg[2], img, final_T, n_contrib,
-                                  (const float2 *)nullptr, (float *)nullptr);
-        else
-            hipLaunchKernelGGL((k_blend<PX, RW, false, false>), grid, block, 0, st, rec, vals, ranges, order, c, bg[0], bg[1],
-                               bg[2], img, final_T, n_contrib, nullptr, nullptr);
-    }
-}
-
-// Wavefront pixel region: PX pixels per lane in one column, RW columns wide.  Default 1 x 8
-// (an 8x8 square per wavefront); D4DGS_BLEND=<px>x<rw> selects 1x16, 2x8, 2x16 or 4x16.
-int blend_variant() {
-    static const int v = [] {
-        const char *e = getenv("D4DGS_BLEND");
-        int px = 1, rw = 8;
-        if (e && sscanf(e, "%dx%d", &px, &rw) != 2) px = 1, rw = 8;
-        const int code = px * 100 + rw;
-        return (code == 108 || code == 116 || code == 208 || code == 216 || code == 416) ? code : 108;
-    }();
-    return v;
+    const float2 *no_mdot = nullptr;
+    float *no_flow = nullptr;
+    if (e0)
+        hipExtLaunchKernelGGL((k_blend<PX, RW, STATE, false>), grid, block, 0, st, e0, e1, 0, rec, vals, ranges, order,
+                              c, bg[0], bg[1], bg[2], img, final_T, n_contrib, no_mdot, no_flow);
+    else
+        hipLaunchKernelGGL((k_blend<PX, RW, STATE, false>), grid, block, 0, st, rec, vals, ranges, order, c, bg[0],
+                           bg[1], bg[2], img, final_T, n_contrib, no_mdot, no_flow);
 }
 
 }  // namespace
@@ -236,13 +211,12 @@ hipError_t launch_blend(const float4 *rec, const uint32_t *vals, const uint32_t 
                         const CamK &c, const float bg[3], float *img, float *final_T, uint32_t *n_contrib,
                         hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (c.TX * c.TY == 0) return hipSuccess;
-    switch (blend_variant()) {
-        case 116: launch_px<1, 16>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1); break;
-        case 208: launch_px<2, 8>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1); break;
-        case 216: launch_px<2, 16>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1); break;
-        case 416: launch_px<4, 16>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1); break;
-        default: launch_px<1, 8>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1); break;
-    }
+    // the wavefront region is a template parameter (PX pixels per lane in one column, RW
+    // columns): 8x8 with one pixel per lane measured fastest of 8x8, 16x4, 8x16 and 16x16
+    if (final_T)
+        launch_px<1, 8, true>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1);
+    else
+        launch_px<1, 8, false>(rec, vals, ranges, order, c, bg, img, final_T, n_contrib, st, e0, e1);
     return hipGetLastError();
 }
 
