@@ -193,7 +193,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restr
             keep = !splat_misses(h0, make_float4(0.f, 0.f, h2.z, h2.w), wx0, wx1, wy0, wy1);
         }
         uint64_t km = __ballot(keep);
-        if (ln == 0) kmask[w] = km;
+        // splats that no pixel of the quadrant blends (behind every pixel's last
+        // contributor, or below 1/255 at every pixel) contribute exact zeros: they are
+        // dropped from the quadrant's mask instead of reduced
+        uint64_t used = km;
         while (km) {
             const int i = 63 - __builtin_clzll(km);  // from the back of the list
             km &= ~(1ull << i);
@@ -201,6 +204,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restr
             const float2 h2 = *reinterpret_cast<const float2 *>(&s2[i]);
             const uint32_t tag = __builtin_amdgcn_readfirstlane(__float_as_uint(h2.y));
             const uint32_t jj = tag & 0x7fffffffu;  // position in the tile's list
+            const uint64_t live = __ballot(jj < nc);
+            if (live == 0) {
+                used &= ~(1ull << i);
+                continue;
+            }
             // the forward's per-splat tests: no "exponent > 0" skip for plain splats
             const uint64_t pos_ok = (tag >> 31) ? ~0ull : 0ull;
             const float dx = sx - h0.x, dy = sy - h0.y;
@@ -208,7 +216,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restr
             const float q = pix_exponent(ct, h1, dy);
             const float e = exp2_fast(q);
             const float alpha = fminf(kAlphaMax, e);
-            const uint64_t ok = __ballot(jj < nc) & (pos_ok | __ballot(!(q > h1.y))) & __ballot(alpha >= kAlphaMin);
+            const uint64_t ok = live & (pos_ok | __ballot(!(q > h1.y))) & __ballot(alpha >= kAlphaMin);
+            if (ok == 0) {
+                used &= ~(1ull << i);
+                continue;
+            }
             const bool okb = __builtin_amdgcn_inverse_ballot_w64(ok);
             const bool unclamped = __builtin_amdgcn_inverse_ballot_w64(ok & __ballot(e <= kAlphaMax));
             const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
@@ -239,6 +251,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restr
                 }
             }
         }
+        if (ln == 0) kmask[w] = used;
         __syncthreads();
         // one thread per staged splat: add the quadrants' sums (fixed order), turn the
         // moments into the gradients of the 2D mean (d power / d m = Q d), the conic
@@ -259,7 +272,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restr
             }
             if (sl < capacity) {  // false only after an instance overflow
                 if (!any) {
-                    zero_slot(ig, sl);  // no pixel of the tile reaches 1/255
+                    zero_slot(ig, sl);  // no pixel of the tile blends it
                 } else {
                     const float4 h3 = s3[tid];
                     const float P0 = m[0], Sx = m[1], Sy = m[2], Sxx = m[3], Sxy = m[4], Syy = m[5];
