@@ -362,6 +362,14 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gam = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
     float gfx = 0.f, gfy = 0.f;  // dL/dmdot from the flow (zero when no flow was rendered)
     const uint32_t o0 = offset[gi];
+    // the scene parameters are loaded first, so that their latency overlaps the slot sum
+    const float q0 = s.quat[gi], q1 = s.quat[n + gi], q2 = s.quat[2 * n + gi], q3 = s.quat[3 * n + gi];
+    const float sc[3] = {s.scale[gi], s.scale[n + gi], s.scale[2 * n + gi]};
+    const float mu[3] = {s.mean[gi], s.mean[n + gi], s.mean[2 * n + gi]};
+    const float v[3] = {s.velocity[gi], s.velocity[n + gi], s.velocity[2 * n + gi]};
+    const float op = s.opacity[gi], mut = s.t_mean[gi], st = s.t_scale[gi];
+    const float4 r0 = rec[3 * (size_t)gi], r1 = rec[3 * (size_t)gi + 1];
+#pragma unroll 4
     for (uint32_t k = 0; k < cnt; ++k) {
         const size_t sl = 3 * (size_t)(o0 + k);
         const float4 a = ig[sl], b4 = ig[sl + 1], c4 = ig[sl + 2];
@@ -372,7 +380,6 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
         gfy += c4.z;
     }
     // 2. recompute the forward quantities (camera stage + time stage)
-    const float q0 = s.quat[gi], q1 = s.quat[n + gi], q2 = s.quat[2 * n + gi], q3 = s.quat[3 * n + gi];
     const float n2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
     const float nrm = sqrtf(n2);
     const float qw = q0 / nrm, qx = q1 / nrm, qy = q2 / nrm, qz = q3 / nrm;
@@ -386,16 +393,12 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     Rq[6] = 2.0f * (qx * qz - qw * qy);
     Rq[7] = 2.0f * (qy * qz + qw * qx);
     Rq[8] = 1.0f - 2.0f * (qx * qx + qy * qy);
-    const float sc[3] = {s.scale[gi], s.scale[n + gi], s.scale[2 * n + gi]};
-    const float mu[3] = {s.mean[gi], s.mean[n + gi], s.mean[2 * n + gi]};
-    const float v[3] = {s.velocity[gi], s.velocity[n + gi], s.velocity[2 * n + gi]};
     const float *R = c.R;
     float p[3], u[3];
     for (int i = 0; i < 3; ++i) {
         p[i] = R[3 * i + 0] * mu[0] + R[3 * i + 1] * mu[1] + R[3 * i + 2] * mu[2] + c.T[i];
         u[i] = R[3 * i + 0] * v[0] + R[3 * i + 1] * v[1] + R[3 * i + 2] * v[2];
     }
-    const float op = s.opacity[gi], mut = s.t_mean[gi], st = s.t_scale[gi];
     const float tau = t - mut;
     const float w = expf(-0.5f * ((tau * tau) / (st * st)));
     const float pt[3] = {p[0] + tau * u[0], p[1] + tau * u[1], p[2] + tau * u[2]};
@@ -412,7 +415,6 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
     const float J00 = c.fx / z, J11 = c.fy / z;
     const float J02 = -(c.fx * tx) / (z * z), J12 = -(c.fy * ty) / (z * z);
     // conic (A, B, C) of the record
-    const float4 r0 = rec[3 * (size_t)gi], r1 = rec[3 * (size_t)gi + 1];
     const float QA = r0.z, QB = r0.w, QC = r1.x;
 
     // 3. chain rule, time stage
