@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-times", action="store_true", help="skip the multi-timestamp batch measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the side sweeps (camera cache off, one camera's 300 frames)")
+    ap.add_argument("--no-steps", action="store_true",
+                    help="skip the 8-view 800x800 (100k, SH1) and 4-view 2704x2028 (2M, SH3) forward+backward steps")
     ap.add_argument("--cpu-frames", type=int, default=100)
     ap.add_argument("--bwd-frames", type=int, default=40)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -124,7 +128,7 @@ def touch_streams(k):
     torch.cuda.synchronize()
 
 
-def sweep(args, ds, cams, times, render, S, time_blends, tile_order, streams=None):
+def sweep(args, ds, cams, times, render, S, time_blends, tile_order, streams=None, cache=True):
     """The camera-major sweep: `args.warmup` untimed steps, then `args.steps` timed ones.
     Frames are independent, so consecutive frames go round-robin to S HIP streams
     (default priority), each with its own frame buffers and camera-stage cache: one
@@ -135,7 +139,7 @@ def sweep(args, ds, cams, times, render, S, time_blends, tile_order, streams=Non
     import torch
 
     W, H = cams[0].width, cams[0].height
-    rends = [render.Renderer(ds, W, H, capacity=4 * ds.n, cache=True, tile_order=tile_order) for _ in range(S)]
+    rends = [render.Renderer(ds, W, H, capacity=4 * ds.n, cache=cache, tile_order=tile_order) for _ in range(S)]
     streams = streams or [torch.cuda.Stream() for _ in range(S)]
     handles = [st.cuda_stream for st in streams]
     nfr = len(times)
@@ -210,6 +214,78 @@ def fwd_bwd(args, ds, cams, render, inputs):
     assert not any(r.overflowed() for r in rends)
     return {"frames_per_s": round(len(views) / el, 2), "ms_per_frame": round(1000 * el / len(views), 4),
             "frames": len(views), "camera_cache": False, "streams": S}
+
+
+def side_sweeps(args, ds, cams, times, render):
+    """The headline sweep with the camera-stage cache off (the camera stage then runs for
+    every frame), and one camera's 300 frames alone (camera 10: the analogue of a fixed
+    test view's video), both on the sweep's streams."""
+    import types
+
+    S = max(1, args.streams)
+    off = types.SimpleNamespace(warmup=2, steps=len(cams))
+    el, _, _ = sweep(off, ds, cams, times, render, S, False, args.tile_order, cache=False)
+    one = types.SimpleNamespace(warmup=2, steps=1)
+    el1, _, _ = sweep(one, ds, [cams[10]], times, render, S, False, args.tile_order)
+    return {"cache_off_frames_per_s": round(len(cams) * len(times) / el, 2),
+            "camera10_frames_per_s": round(len(times) / el1, 2)}
+
+
+def view_steps(inputs, render):
+    """Forward + backward steps of the two training-style workloads, on two streams as in
+    the forward + backward phase (one view's forward overlaps the previous view's
+    backward; the backward passes add into one set of gradients in order):
+    8 views at 800x800 of 100k Gaussians (SH1), and 4 views at 2704x2028 of 2M Gaussians
+    (SH3), with the step's peak device memory beyond the resident scene."""
+    import numpy as np
+    import torch
+
+    out = {}
+    for name in ("c3_8x800x800_100k", "c5_4x2704x2028_2M"):
+        if name.startswith("c3"):
+            sc, views, _ = inputs.config3()
+        else:
+            sc, views = inputs.config5_scene(), inputs.config5_views()
+        ds = render.DeviceScene.from_inputs(sc)
+        scene_bytes = sum(x.numel() * x.element_size() for x in ds.t.values())
+        del sc
+        W, H = views[0][0].width, views[0][0].height
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        rends = [render.Renderer(ds, W, H, cache=False, keep_state=True) for _ in range(2)]
+        streams = [torch.cuda.Stream() for _ in range(2)]
+        grads = render.grads_like(ds)
+        dL = torch.from_numpy(inputs.upstream_grad(11, W, H)).cuda()
+
+        def step():
+            prev = None
+            for i, (cam, t) in enumerate(views):
+                r = i % 2
+                with torch.cuda.stream(streams[r]):
+                    rends[r].render(cam, t)
+                    if prev is not None:
+                        streams[r].wait_event(prev)
+                    rends[r].backward(cam, t, dL, grads)
+                    prev = torch.cuda.Event()
+                    prev.record(streams[r])
+
+        step()
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        assert not any(r.overflowed() for r in rends)
+        out[name] = {"views": len(views), "ms_per_step": round(1e3 * el, 3),
+                     "views_per_s": round(len(views) / el, 1),
+                     "peak_step_bytes": int(torch.cuda.max_memory_allocated() - base),
+                     "scene_bytes": int(scene_bytes)}
+        del rends, grads, ds, dL
+        torch.cuda.empty_cache()
+    return out
 
 
 def times_batch(args, ds, cams, render):
@@ -321,8 +397,12 @@ def main():
     }
     if not args.no_bwd:
         out["fwd_bwd"] = fwd_bwd(args, ds, cams, render, inputs)
+    if not args.no_extras:
+        out["sweep_extras"] = side_sweeps(args, ds, cams, times, render)
     if not args.no_times:
         out["times_batch"] = times_batch(args, ds, cams, render)
+    if not args.no_steps:
+        out["view_steps"] = view_steps(inputs, render)
     if not args.no_serve:
         try:
             from paper_2503_22159_amd import serve_bench
