@@ -40,6 +40,31 @@ CamK make_camk(const d4dgs_camera &c) {
     return k;
 }
 
+static bool finite_f(float x) { return std::isfinite(x); }
+
+bool image_size_ok(int32_t w, int32_t h) {
+    // tile rectangles pack tile coordinates into 16 bits, and the per-tile launches have
+    // 4 workgroups per tile in a grid of 32-bit size
+    if (w <= 0 || h <= 0 || w > 65535 * kTile || h > 65535 * kTile) return false;
+    const int64_t tiles = (int64_t)((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
+    return tiles <= ((int64_t)1 << 26);
+}
+
+const char *camera_problem(const d4dgs_camera &c) {
+    if (!image_size_ok(c.width, c.height)) return "camera size out of range";
+    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !finite_f(c.fx) || !finite_f(c.fy) || !finite_f(c.cx) ||
+        !finite_f(c.cy))
+        return "camera intrinsics invalid";
+    if (!(c.tan_fovx > 0.f) || !(c.tan_fovy > 0.f) || !finite_f(c.tan_fovx) || !finite_f(c.tan_fovy))
+        return "camera field of view invalid";
+    if (!(c.znear > 0.f) || !finite_f(c.znear)) return "znear must be > 0";
+    for (int i = 0; i < 9; ++i)
+        if (!finite_f(c.R[i])) return "camera rotation not finite";
+    for (int i = 0; i < 3; ++i)
+        if (!finite_f(c.T[i]) || !finite_f(c.campos[i])) return "camera position not finite";
+    return nullptr;
+}
+
 SceneK make_scenek(const d4dgs_scene &s) {
     SceneK k;
     k.n = s.n;
@@ -72,8 +97,6 @@ d4dgs_status hip_status(hipError_t e, const char *where) {
     return D4DGS_ERR_HIP;
 }
 
-bool finite(float x) { return std::isfinite(x); }
-
 d4dgs_status check_scene(const d4dgs_scene *s) {
     if (!s) return fail(D4DGS_ERR_INVALID_ARG, "scene is NULL");
     if (s->n < 0) return fail(D4DGS_ERR_INVALID_ARG, "scene n < 0");
@@ -87,19 +110,8 @@ d4dgs_status check_scene(const d4dgs_scene *s) {
 
 d4dgs_status check_camera(const d4dgs_camera *c) {
     if (!c) return fail(D4DGS_ERR_INVALID_ARG, "camera is NULL");
-    if (c->width <= 0 || c->height <= 0 || c->width > 65535 * kTile || c->height > 65535 * kTile)
-        return fail(D4DGS_ERR_INVALID_ARG, "camera size out of range");
-    if (!(c->fx > 0.f) || !(c->fy > 0.f) || !finite(c->fx) || !finite(c->fy) || !finite(c->cx) ||
-        !finite(c->cy))
-        return fail(D4DGS_ERR_INVALID_ARG, "camera intrinsics invalid");
-    if (!(c->tan_fovx > 0.f) || !(c->tan_fovy > 0.f) || !finite(c->tan_fovx) || !finite(c->tan_fovy))
-        return fail(D4DGS_ERR_INVALID_ARG, "camera field of view invalid");
-    if (!(c->znear > 0.f) || !finite(c->znear)) return fail(D4DGS_ERR_INVALID_ARG, "znear must be > 0");
-    for (int i = 0; i < 9; ++i)
-        if (!finite(c->R[i])) return fail(D4DGS_ERR_INVALID_ARG, "camera rotation not finite");
-    for (int i = 0; i < 3; ++i)
-        if (!finite(c->T[i]) || !finite(c->campos[i])) return fail(D4DGS_ERR_INVALID_ARG, "camera position not finite");
-    return D4DGS_OK;
+    const char *why = camera_problem(*c);
+    return why ? fail(D4DGS_ERR_INVALID_ARG, why) : D4DGS_OK;
 }
 
 d4dgs_status check_splats(const d4dgs_splats *sp, int n) {
@@ -137,7 +149,7 @@ const char *d4dgs_last_error(void) { return g_err.c_str(); }
 
 d4dgs_status d4dgs_workspace_size(int32_t n, int32_t width, int32_t height, int64_t max_instances, size_t *bytes) {
     if (!bytes) return fail(D4DGS_ERR_INVALID_ARG, "bytes is NULL");
-    if (n < 0 || width <= 0 || height <= 0 || max_instances < 1 || max_instances > (int64_t)0x7fffffff)
+    if (n < 0 || !image_size_ok(width, height) || max_instances < 1 || max_instances > (int64_t)0x7fffffff)
         return fail(D4DGS_ERR_INVALID_ARG, "workspace sizes out of range");
     *bytes = sort_workspace_bytes(n, max_instances, ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile));
     return D4DGS_OK;
@@ -191,7 +203,7 @@ d4dgs_status d4dgs_bin_sort(const d4dgs_splats *splats, int32_t n, int32_t width
     if (n < 0) return fail(D4DGS_ERR_INVALID_ARG, "n < 0");
     D4_TRY(check_splats(splats, n));
     D4_TRY(check_bins(bins));
-    if (width <= 0 || height <= 0 || width > 65535 * kTile || height > 65535 * kTile)
+    if (!image_size_ok(width, height))
         return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
     if (!workspace) return fail(D4DGS_ERR_INVALID_ARG, "workspace is NULL");
     d4dgs_camera dummy;
@@ -235,7 +247,7 @@ d4dgs_status render_fwd_impl(const d4dgs_splats *splats, const d4dgs_bins *bins,
                              hipEvent_t e1, d4dgs_stream stream) {
     if (!splats || !splats->rec) return fail(D4DGS_ERR_INVALID_ARG, "splats is NULL");
     D4_TRY(check_bins(bins));
-    if (width <= 0 || height <= 0 || width > 65535 * kTile || height > 65535 * kTile)
+    if (!image_size_ok(width, height))
         return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
     if (!bg || !img) return fail(D4DGS_ERR_INVALID_ARG, "bg or img is NULL");
     if ((final_T == nullptr) != (n_contrib == nullptr))
@@ -329,7 +341,7 @@ d4dgs_status d4dgs_render_fwd_flow(const d4dgs_splats *splats, const d4dgs_bins 
     if (!splats || !splats->rec) return fail(D4DGS_ERR_INVALID_ARG, "splats is NULL");
     if (!splats->mdot) return fail(D4DGS_ERR_INVALID_ARG, "render_fwd_flow: splats->mdot is NULL");
     D4_TRY(check_bins(bins));
-    if (width <= 0 || height <= 0 || width > 65535 * kTile || height > 65535 * kTile)
+    if (!image_size_ok(width, height))
         return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
     if (!bg || !img || !flow) return fail(D4DGS_ERR_INVALID_ARG, "bg, img or flow is NULL");
     if ((final_T == nullptr) != (n_contrib == nullptr))

@@ -33,6 +33,10 @@ struct CamK {
 };
 
 CamK make_camk(const d4dgs_camera &c);
+// width and height the kernels handle
+bool image_size_ok(int32_t w, int32_t h);
+// NULL if the camera is usable, else what is wrong with it
+const char *camera_problem(const d4dgs_camera &c);
 
 // --- wave64 helpers ---------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -371,10 +371,8 @@ d4dgs_status d4dgs_serve_submit(d4dgs_server *s, const d4dgs_camera *cam, float 
         set_error("serve_submit: NULL argument");
         return D4DGS_ERR_INVALID_ARG;
     }
-    if (cam->width <= 0 || cam->height <= 0 || cam->width > 65535 * kTile || cam->height > 65535 * kTile ||
-        !(cam->fx > 0.f) || !(cam->fy > 0.f) || !(cam->znear > 0.f) || !(cam->tan_fovx > 0.f) ||
-        !(cam->tan_fovy > 0.f)) {
-        set_error("serve_submit: invalid camera");
+    if (const char *why = camera_problem(*cam)) {
+        set_error(std::string("serve_submit: ") + why);
         return D4DGS_ERR_INVALID_ARG;
     }
     std::lock_guard<std::mutex> lk(s->mu);

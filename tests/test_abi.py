@@ -57,3 +57,42 @@ def test_host_argument_checks():
     cam = B.Camera()
     assert B.lib.d4dgs_project(C.byref(s), C.byref(cam), 0.0, None, None, None) == B.ERR_INVALID_ARG
     assert B.lib.d4dgs_serve_create(None, None, None) == B.ERR_INVALID_ARG
+
+
+def test_camera_checks_reject_bad_cameras():
+    """The camera checks (shared by d4dgs_project and the server's submit) run on the host
+    before any GPU work: non-finite or non-positive fields and image sizes beyond what the
+    kernels index are rejected with INVALID_ARG and a message."""
+    import math
+
+    from paper_2503_22159_amd import binding as B
+    from paper_2503_22159_amd import inputs
+
+    s = B.Scene()
+    s.n, s.sh_degree = 0, 0
+    good = inputs.look_at((0.0, 0.0, -6.0), width=64, height=48)
+
+    def project(mutate):
+        cam = B.camera_struct(good)
+        mutate(cam)
+        return B.lib.d4dgs_project(C.byref(s), C.byref(cam), 0.5, None, None, None)
+
+    # a good camera passes the camera checks and stops at the missing splats
+    assert project(lambda c: None) == B.ERR_INVALID_ARG and "splats" in B.last_error()
+    cases = [
+        (lambda c: setattr(c, "width", 0), "size"),
+        (lambda c: setattr(c, "height", 65535 * 16 + 1), "size"),
+        # each side within 65535 tiles, but more tiles than a launch grid can index
+        (lambda c: (setattr(c, "width", 65535 * 16), setattr(c, "height", 65535 * 16)), "size"),
+        (lambda c: setattr(c, "fx", 0.0), "intrinsics"),
+        (lambda c: setattr(c, "cy", math.nan), "intrinsics"),
+        (lambda c: setattr(c, "tan_fovy", -1.0), "field of view"),
+        (lambda c: setattr(c, "znear", 0.0), "znear"),
+        (lambda c: c.R.__setitem__(4, math.inf), "rotation"),
+        (lambda c: c.campos.__setitem__(1, math.nan), "position"),
+    ]
+    for mutate, word in cases:
+        assert project(mutate) == B.ERR_INVALID_ARG, word
+        assert word in B.last_error(), (word, B.last_error())
+    b = C.c_size_t(0)
+    assert B.lib.d4dgs_workspace_size(10, 65535 * 16, 65535 * 16, 1000, C.byref(b)) == B.ERR_INVALID_ARG
