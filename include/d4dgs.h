@@ -349,11 +349,12 @@ d4dgs_status d4dgs_serve_submit(d4dgs_server *s, const d4dgs_camera *cam, float 
                                 uint64_t *ticket);
 /* *done = 1 once the image is complete (stats filled, the ticket is then released). */
 d4dgs_status d4dgs_serve_poll(d4dgs_server *s, uint64_t ticket, int32_t *done, d4dgs_req_stats *st);
-/* Blocks until done or timeout_ns passes (TIMEOUT); fills st and releases the ticket. */
+/* Blocks until done or timeout_ns passes (TIMEOUT); fills st and releases the ticket.
+ * NOT_FOUND if the ticket is unknown or was released meanwhile by another call. */
 d4dgs_status d4dgs_serve_wait(d4dgs_server *s, uint64_t ticket, int64_t timeout_ns, d4dgs_req_stats *st);
 d4dgs_status d4dgs_serve_stats_get(d4dgs_server *s, d4dgs_serve_stats *st);
-/* Cancels queued requests (status INVALID_ARG... reported as NOT_FOUND afterwards),
- * drains in-flight ones, frees the arena and streams. */
+/* Cancels the requests not yet admitted, waits for the admitted ones to finish, then
+ * frees the arena and streams; every ticket is invalid afterwards. */
 d4dgs_status d4dgs_serve_destroy(d4dgs_server *s);
 
 #ifdef __cplusplus

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -223,8 +224,14 @@ void d4dgs_server::launch(Batch &b) {
     if (e != hipSuccess) {
         set_error(std::string("serve launch: ") + hipGetErrorString(e));
         (void)hipStreamSynchronize(st);
-        for (Req *r : b.reqs) finish(r, D4DGS_ERR_HIP);
+        if (b.ev) (void)hipEventDestroy(b.ev);
+        b.ev = nullptr;
+        for (Req *r : b.reqs) {
+            inflight_reqs--;
+            finish(r, D4DGS_ERR_HIP);
+        }
         b.reqs.clear();
+        cv_done.notify_all();
     }
     stats.batches++;
 }
@@ -232,8 +239,17 @@ void d4dgs_server::launch(Batch &b) {
 // Returns true if the batch finished (and was retired).
 bool d4dgs_server::retire_one(Batch &b) {
     if (b.reqs.empty()) return true;
-    if (hipEventQuery(b.ev) != hipSuccess) return false;
+    const hipError_t q = hipEventQuery(b.ev);
+    if (q == hipErrorNotReady) return false;
     (void)hipEventDestroy(b.ev);
+    if (q != hipSuccess) {  // the batch's work failed: its requests end with the error
+        set_error(std::string("serve batch: ") + hipGetErrorString(q));
+        for (Req *r : b.reqs) {
+            inflight_reqs--;
+            finish(r, D4DGS_ERR_HIP);
+        }
+        return true;
+    }
     for (Req *r : b.reqs) {
         const int64_t ninst = pinned[2 * r->slot];
         const uint32_t status = (uint32_t)(pinned[2 * r->slot + 1] & 0xffffffff);
@@ -375,6 +391,10 @@ d4dgs_status d4dgs_serve_submit(d4dgs_server *s, const d4dgs_camera *cam, float 
         set_error(std::string("serve_submit: ") + why);
         return D4DGS_ERR_INVALID_ARG;
     }
+    if (!std::isfinite(t)) {
+        set_error("serve_submit: t not finite");
+        return D4DGS_ERR_INVALID_ARG;
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
         set_error("serve_submit: server is shutting down");
@@ -427,14 +447,22 @@ d4dgs_status d4dgs_serve_wait(d4dgs_server *s, uint64_t ticket, int64_t timeout_
         set_error("serve_wait: unknown ticket");
         return D4DGS_ERR_NOT_FOUND;
     }
-    Req *r = it->second.get();
-    const bool ok = s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), [r] { return r->done; });
+    // the ticket is looked up again after every wake-up: another thread may have taken it
+    const bool ok = s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), [s, ticket] {
+        auto f = s->reqs.find(ticket);
+        return f == s->reqs.end() || f->second->done;
+    });
     if (!ok) {
         set_error("serve_wait: timeout");
         return D4DGS_ERR_TIMEOUT;
     }
-    if (st) *st = r->st;
-    s->reqs.erase(ticket);
+    it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) {
+        set_error("serve_wait: ticket taken by another call");
+        return D4DGS_ERR_NOT_FOUND;
+    }
+    if (st) *st = it->second->st;
+    s->reqs.erase(it);
     return D4DGS_OK;
 }
 
