@@ -46,8 +46,14 @@ class DeviceScene:
         self.t = {k: tensors[k].contiguous() for k in FIELDS}
         for k in FIELDS:
             assert self.t[k].dtype == torch.float32 and self.t[k].is_cuda, k
-        self.n = int(self.t["opacity"].shape[0])
+        self.n = int(self.t["opacity"].numel())
         self.sh_degree = int(sh_degree)
+        assert 0 <= self.sh_degree <= 3, "sh_degree must be 0..3"
+        # the kernels index these planar arrays by n: a short one would be read out of bounds
+        per = {"mean": 3, "scale": 3, "quat": 4, "opacity": 1, "t_mean": 1, "t_scale": 1, "velocity": 3,
+               "sh": 3 * (self.sh_degree + 1) ** 2}
+        for k, m in per.items():
+            assert self.t[k].numel() == m * self.n, (k, tuple(self.t[k].shape), m, self.n)
 
     @classmethod
     def from_inputs(cls, scene, device="cuda"):
