@@ -10,15 +10,20 @@
  *                     Alg. 1; Eq. 9-15 (projection first, temporal processing
  *                     deferred: temporal opacity falloff and screen-space motion
  *                     are applied after the spatial projection).
- *   d4dgs_bin_sort    tile binning of the projected splats and a depth-keyed LSD
- *                     radix sort into per-tile front-to-back lists (the tiled
- *                     rasteriser the paper adopts from 3D Gaussian Splatting, Sec. 3.2.2).
+ *   d4dgs_bin_sort    tile binning of the projected splats and a depth-keyed sort of
+ *                     each tile's list, front to back (the tiled rasteriser the paper
+ *                     adopts from 3D Gaussian Splatting, Sec. 3.2.2): keys of up to 512
+ *                     per tile are ranked, longer lists radix-sorted.
  *   d4dgs_render_fwd  per-tile front-to-back alpha blending, Eq. 4.
  *   d4dgs_render_bwd  adjoint of the three stages above (the differentiable
  *                     pipeline of Fig. 3): replays each pixel's transmittance in
  *                     reverse from its final value and returns gradients for every
  *                     per-Gaussian parameter, including mu_t, s_t and the velocity.
  *   d4dgs_serve_*     a continuous-batching render server over one resident scene.
+ *   d4dgs_render_times  T frames of one camera at T times (one camera stage).
+ *   d4dgs_render_fwd_flow, d4dgs_flow_loss, d4dgs_render_bwd_flow
+ *                     the rendered optical flow and the flow-gradient guided
+ *                     consistency loss (Sec. 3.3, Eq. 16-17) with their adjoints.
  *
  * Conventions
  *  - Every pointer marked (device) is device memory owned by the caller; the library
