@@ -207,3 +207,27 @@ def test_gradients_against_gpu_finite_differences(R):
             assert abs(fd - an) <= 0.05 * abs(an) + 2e-2, (k, i, fd, an)
             checked += 1
     assert checked == 18
+
+
+def test_backward_of_empty_and_all_culled_frames(R):
+    """The adjoint of a frame with no Gaussians, and of one where every Gaussian is
+    temporally culled, runs and adds exact zeros (the image is the background alone)."""
+    import torch
+
+    sc, cam, t = inputs.config1()
+    dL = torch.from_numpy(inputs.upstream_grad(31, cam.width, cam.height)).cuda()
+    empty = sc.subset(np.arange(0))
+    ds = R.DeviceScene.from_inputs(empty)
+    img, st = R.render_forward(ds, cam, t, (0.3, 0.2, 0.1))
+    g = R.render_backward(ds, cam, t, (0.3, 0.2, 0.1), st, dL)
+    torch.cuda.synchronize()
+    assert all(g[k].numel() == 0 for k in GROUPS)
+    far = sc.subset(np.arange(sc.n))
+    far.t_scale[:] = np.float32(1e-4)
+    ds = R.DeviceScene.from_inputs(far)
+    img, st = R.render_forward(ds, cam, np.float32(5.0), (0.3, 0.2, 0.1))
+    g = R.render_backward(ds, cam, np.float32(5.0), (0.3, 0.2, 0.1), st, dL, R.grads_like(ds, split_stats=True))
+    torch.cuda.synchronize()
+    assert int(st.num_inst.item()) == 0
+    for k in GROUPS + ("split_grad_t", "split_grad_xyz", "split_count"):
+        assert not torch.any(g[k] != 0), k
