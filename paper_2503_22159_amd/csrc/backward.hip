@@ -141,6 +141,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restr
     const int px = qx0 + (ln & 7), py = qy0 + (ln >> 3);
     const float sx = (float)px + 0.5f, sy = (float)py + 0.5f;
     const float wx0 = (float)qx0 + 0.5f, wx1 = wx0 + 7.0f, wy0 = (float)qy0 + 0.5f, wy1 = wy0 + 7.0f;
+    // the forward's exponent: coefficients about the quadrant's centre, the lane's offset
+    const float xc = (float)qx0 + 4.0f, yc = (float)qy0 + 4.0f;
+    const PixUV pu = pix_uv((float)(ln & 7) - 3.5f, (float)(ln >> 3) - 3.5f);
     const bool in = px < c.W && py < c.H;
     const size_t pi = (size_t)py * c.W + px;
     float Tc = in ? final_T[pi] : 1.0f;
@@ -167,6 +170,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restr
     __shared__ uint32_t sslot[kWave];
     __shared__ float2 s4[FLOW ? kWave : 1];  // mdot
     __shared__ uint64_t kmask[4];
+    __shared__ float4 sqc[4][kWave];  // per quadrant: {K, Lx, Ly, -} of the staged splats it keeps
     __shared__ float red[4 * kWave * NR];
     for (uint32_t jb = start + nmax; jb > start;) {
         const uint32_t j0 = jb - start > (uint32_t)kWave ? jb - kWave : start;
@@ -191,7 +195,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restr
         if ((uint32_t)ln < nb) {
             const float4 h0 = s0[ln], h2 = s2[ln];
             keep = !splat_misses(h0, make_float4(0.f, 0.f, h2.z, h2.w), wx0, wx1, wy0, wy1);
+            if (keep) sqc[w][ln] = square_coeffs(h0, s1[ln], xc, yc);
         }
+        // sqc[w] is written and read by this wavefront alone (LDS accesses of a wavefront
+        // complete in order); keep the compiler from moving the reads above the writes
+        __builtin_amdgcn_wave_barrier();
         uint64_t km = __ballot(keep);
         // splats that no pixel of the quadrant blends (behind every pixel's last
         // contributor, or below 1/255 at every pixel) contribute exact zeros: they are
@@ -212,8 +220,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restr
             // the forward's per-splat tests: no "exponent > 0" skip for plain splats
             const uint64_t pos_ok = (tag >> 31) ? ~0ull : 0ull;
             const float dx = sx - h0.x, dy = sy - h0.y;
-            const ColTerms ct = col_terms(h0, h1, dx);
-            const float q = pix_exponent(ct, h1, dy);
+            const float4 kc = sqc[w][i];
+            const float q = sq_exponent(kc.x, kc.y, kc.z, h0.z, h0.w, h1.x, pu);
             const float e = exp2_fast(q);
             const float alpha = fminf(kAlphaMax, e);
             const uint64_t ok = live & (pos_ok | __ballot(!(q > h1.y))) & __ballot(alpha >= kAlphaMin);

@@ -79,9 +79,8 @@ __device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_lo
 // la = log2(amax), so that for d = sample - m
 //   q = qa dx^2 + qb dx dy + qc dy^2 + la = log2(amax) + log2(e) * power,
 //   alpha = min(0.99, 2^q),  and "power > 0" is "q > la".
-// Per lane the terms that depend only on dx are formed once and shared by the lane's
-// pixels, which lie in one column:  A0 = qa dx dx + la,  B0 = qb dx,
-//   q = (qc dy + B0) dy + A0.
+// Over a wavefront's pixel region q is evaluated as a polynomial in the pixel's offset
+// from the region's centre (see square_coeffs).
 //
 // f2.z, f2.w are the half-extents (x, y) of the ellipse where alpha can reach 1/255:
 // amax exp(power) >= 1/255 needs power >= -L, L = ln(255 amax), and -power =
@@ -132,19 +131,38 @@ __device__ __forceinline__ bool splat_misses(const float4 &f0, const float4 &f2,
     return f2.z < 0.0f || f0.x + f2.z < x0 || f0.x - f2.z > x1 || f0.y + f2.w < y0 || f0.y - f2.w > y1;
 }
 
-struct ColTerms {
-    float A0, B0;
-};
-
-__device__ __forceinline__ ColTerms col_terms(const float4 &f0, const float4 &f1, float dx) {
-    ColTerms t;
-    t.A0 = __builtin_fmaf(f0.z * dx, dx, f1.y);
-    t.B0 = f0.w * dx;
-    return t;
+// The exponent over one wavefront's pixel region, expanded about the region's centre
+// (xc, yc): with (dx, dy) = (xc, yc) - m and the pixel's offset (u, v) from the centre,
+//   q = K + Lx u + Ly v + qa u^2 + qb u v + qc v^2,
+//   K = qa dx^2 + qb dx dy + qc dy^2 + la,  Lx = 2 qa dx + qb dy,  Ly = qb dx + 2 qc dy.
+// K, Lx, Ly are formed once per (region, splat) -- by the forward while it stages a
+// batch, by the backward for each of its quadrants -- with these same instructions, and
+// q per pixel by sq_exponent (five FMAs with the lane's constants u, v, u^2, u v, v^2,
+// all exact), so the forward and the backward take every decision on the same FP32
+// value.  Offsets from the centre (|u|, |v| <= 3.5 on an 8 x 8 square) keep the terms
+// small: against an FP64 evaluation the error of q stays within 1e-4 (log2 units).
+__device__ __forceinline__ float4 square_coeffs(const float4 &f0, const float4 &f1, float xc, float yc) {
+    const float dx = xc - f0.x, dy = yc - f0.y;
+    const float qbdy = f0.w * dy;
+    const float Lx = __builtin_fmaf(2.0f * f0.z, dx, qbdy);
+    const float Ly = __builtin_fmaf(2.0f * f1.x, dy, f0.w * dx);
+    const float K = __builtin_fmaf(__builtin_fmaf(f0.z, dx, qbdy), dx, __builtin_fmaf(f1.x * dy, dy, f1.y));
+    return make_float4(K, Lx, Ly, 0.0f);
 }
 
-__device__ __forceinline__ float pix_exponent(const ColTerms &t, const float4 &f1, float dy) {
-    return __builtin_fmaf(__builtin_fmaf(f1.x, dy, t.B0), dy, t.A0);
+// a lane's pixel as an offset from the region's centre
+struct PixUV {
+    float u, v, uu, uv, vv;
+};
+
+__device__ __forceinline__ PixUV pix_uv(float u, float v) { return {u, v, u * u, u * v, v * v}; }
+
+// q at pixel p of a splat with region coefficients (K, Lx, Ly) and exponent constants
+// (qa, qb, qc)
+__device__ __forceinline__ float sq_exponent(float K, float Lx, float Ly, float qa, float qb, float qc,
+                                             const PixUV &p) {
+    return __builtin_fmaf(qc, p.vv, __builtin_fmaf(qb, p.uv, __builtin_fmaf(qa, p.uu,
+                          __builtin_fmaf(Ly, p.v, __builtin_fmaf(Lx, p.u, K)))));
 }
 
 // --- tile order of the per-tile launches ---------------------------------------------
