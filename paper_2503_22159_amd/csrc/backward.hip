@@ -1,9 +1,10 @@
 // Adjoint of the render path (the differentiable pipeline of Fig. 3).
 //
-// k_blend_bwd   one wavefront per 16x16 tile, four pixels per lane, walking the tile's
-//               list from the wave's last contributor back to the front.  Each pixel's
-//               transmittance is replayed backwards from its final value,
-//               T_i = T_{i+1} / (1 - alpha_i), and, with g = dL/dC the pixel's upstream
+// k_blend_bwd   one 4-wave workgroup per 16x16 tile, a wavefront per 8x8 quadrant, one
+//               pixel per lane, walking the tile's list from the tile's last contributor
+//               back to the front.  Each pixel's transmittance is replayed backwards
+//               from its final value, T_i = T_{i+1} / (1 - alpha_i), and, with g = dL/dC
+//               the pixel's upstream
 //               gradient and S_i = sum_{j>i} c_j alpha_j T_j + T_final bg the colour
 //               behind splat i, the scalar g.S_i is carried along, so
 //                 dL/dc_i     = g alpha_i T_i
@@ -119,8 +120,10 @@ __device__ __forceinline__ void wave_sum9(const float v[9], float &x, float &y) 
 // over four wavefronts shortens the serial chain of the longest tiles fourfold.
 constexpr int kBwdThreads = 4 * kWave;
 
+// The colour-only kernel is held to 64 VGPRs (8 waves per SIMD; it fits without
+// spilling); the flow kernel keeps its larger register set.
 template <bool FLOW>
-__global__ __launch_bounds__(kBwdThreads) void k_blend_bwd(const float4 *__restrict__ rec,
+__global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(FLOW ? 1 : 8))) void k_blend_bwd(const float4 *__restrict__ rec,
                                                            const uint32_t *__restrict__ offset,
                                                            const uint32_t *__restrict__ vals,
                                                            const uint32_t *__restrict__ ranges,
