@@ -21,7 +21,8 @@
 //                    kRankMax keys are sorted by ranking: the keys are unique, so a key's
 //                    sorted position is the number of smaller keys, counted by each thread
 //                    for its own (up to two) keys while the wavefront streams the bucket
-//                    through scalar loads -- no LDS, no barriers.  Larger buckets: stable
+//                    from LDS, two keys per broadcast read (a bucket of at most 64 keys
+//                    takes one wavefront and no barrier).  Larger buckets: stable
 //                    least-significant-digit radix sort over the 64 key bits, 8-bit digits,
 //                    ping-ponging between two global scratch arrays.  Writes
 //                    keys = (tile << 32) | float-bits(depth) and values = gaussian.
@@ -361,29 +362,30 @@ __device__ void block_radix_sort(const uint64_t *src0, uint64_t *a, uint64_t *b,
     }
 }
 
-// Number of keys of b[0, s) below k0 and below k1 (the bucket is read with wave-uniform
-// addresses, i.e. scalar loads).
+// Number of keys of sk[0, s) below k0 and below k1.  sk is the bucket staged in LDS and
+// padded with ~0 (never below a key: a key's high word is a non-negative float's bits) to
+// an even length, so that it is read two keys per broadcast.
 template <bool TWO>
-__device__ __forceinline__ void rank2(const uint64_t *__restrict__ b, uint32_t s, uint64_t k0, uint64_t k1,
-                                      uint32_t &r0, uint32_t &r1) {
+__device__ __forceinline__ void rank2(const uint64_t *sk, uint32_t s, uint64_t k0, uint64_t k1, uint32_t &r0,
+                                      uint32_t &r1) {
+    const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(sk);
+    const uint32_t np = (s + 1) >> 1;
     uint32_t j = 0;
-    for (; j + 16 <= s; j += 16) {
+    for (; j + 4 <= np; j += 4) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const uint64_t kj = b[j + q];
-            r0 += kj < k0;
-            if (TWO) r1 += kj < k1;
+        for (int q = 0; q < 4; ++q) {
+            const ulonglong2 kk = p[j + q];
+            r0 += (kk.x < k0) + (kk.y < k0);
+            if (TWO) r1 += (kk.x < k1) + (kk.y < k1);
         }
     }
-    for (; j < s; ++j) {
-        const uint64_t kj = b[j];
-        r0 += kj < k0;
-        if (TWO) r1 += kj < k1;
+    for (; j < np; ++j) {
+        const ulonglong2 kk = p[j];
+        r0 += (kk.x < k0) + (kk.y < k0);
+        if (TWO) r1 += (kk.x < k1) + (kk.y < k1);
     }
 }
 
-// The bucket is only read here (the radix sort ping-pongs between alt and the key
-// output), so its wave-uniform loads can go through the scalar cache.
 __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint64_t *__restrict__ bucket,
                                                             uint64_t *__restrict__ alt,
                                                             const uint32_t *__restrict__ ranges, int tiles,
@@ -395,6 +397,7 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint64_t *__re
     __shared__ uint32_t cnt[kRadix];
     __shared__ uint32_t wc[(kSortThreads / kWave) * kRadix];
     __shared__ uint32_t tmp4[kSortThreads / kWave];
+    __shared__ uint64_t sk[kRankMax];
     int tile, unused;
     if (!tile_unit(blockIdx.x, TX, TY, 1, order, tile, unused)) return;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
@@ -402,15 +405,29 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint64_t *__re
     const uint32_t tid = threadIdx.x;
     if (s == 0) return;
     if (s <= (uint32_t)kRankMax) {
-        if ((tid & ~(uint32_t)(kWave - 1)) >= s) return;  // a wavefront without keys
+        // the bucket is staged in LDS (coalesced loads) and every key is ranked against it;
+        // a bucket of one wavefront's keys is handled by that wavefront alone, without a
+        // workgroup barrier
         const uint32_t i1 = tid + kSortThreads;
+        const bool one = s <= (uint32_t)kWave;
+        if (one && tid >= (uint32_t)kWave) return;
         const uint64_t k0 = tid < s ? bucket[start + tid] : ~0ull;
         const uint64_t k1 = i1 < s ? bucket[start + i1] : ~0ull;
+        sk[tid] = k0;
+        if (!one) {
+            sk[i1] = k1;
+            __syncthreads();
+            if ((tid & ~(uint32_t)(kWave - 1)) >= s) return;  // a wavefront without keys
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
         uint32_t r0 = 0, r1 = 0;
         if (s <= (uint32_t)kSortThreads)
-            rank2<false>(bucket + start, s, k0, k1, r0, r1);
+            rank2<false>(sk, s, k0, k1, r0, r1);
         else
-            rank2<true>(bucket + start, s, k0, k1, r0, r1);
+            rank2<true>(sk, s, k0, k1, r0, r1);
         if (tid < s) write_out(k0, start + r0, (uint32_t)tile, keys, vals);
         if (i1 < s) write_out(k1, start + r1, (uint32_t)tile, keys, vals);
         return;
