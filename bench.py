@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--streams", type=int, default=4, help="HIP streams the sweep's frames alternate over")
     ap.add_argument("--tile-order", action="store_true",
                     help="launch the sweep's per-tile kernels longest list first (the kernel pass always does)")
+    ap.add_argument("--unfused", action="store_true",
+                    help="sweep through d4dgs_project + d4dgs_bin_sort instead of d4dgs_project_bin")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -151,13 +153,18 @@ def sweep(args, ds, cams, times, render, S, time_blends, tile_order, streams=Non
             e0.record(streams[i % S])
             e1.record(streams[i % S])
 
+    fused = not getattr(args, "unfused", False)
+
     def step(k, ev):
         cam = cams[k % len(cams)]
         for i, t in enumerate(times):
             r = i % S
             rend, h = rends[r], handles[r]
-            rend.project(cam, t, h)
-            rend.bin_sort(h)
+            if fused:
+                rend.project_bin(cam, t, h)
+            else:
+                rend.project(cam, t, h)
+                rend.bin_sort(h)
             rend.blend(stream=h, events=ev[i] if ev else None)
 
     for k in range(args.warmup):
@@ -389,6 +396,7 @@ def main():
         "config": {"workload": "300k Gaussians (SH3, 32 clusters), 1352x1014, 20-camera arc x 300 times, "
                                "camera-stage cache on", "frames_per_step": args.frames, "streams": args.streams,
                    "tile_order": bool(args.tile_order),
+                   "binning": "separate" if args.unfused else "fused",
                    "gaussians": scene.n, "width": W, "height": H},
         "blend_ms_avg": round(blend_ms, 5),
         "kernel_pass": {"streams": 1, "tile_order": True, "frames": frames,

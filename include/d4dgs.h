@@ -14,6 +14,8 @@
  *                     each tile's list, front to back (the tiled rasteriser the paper
  *                     adopts from 3D Gaussian Splatting, Sec. 3.2.2): keys of up to 512
  *                     per tile are ranked, longer lists radix-sorted.
+ *   d4dgs_project_bin d4dgs_project + d4dgs_bin_sort with the binning's counting done
+ *                     by the projection (fewer launches per frame; same output).
  *   d4dgs_render_fwd  per-tile front-to-back alpha blending, Eq. 4.
  *   d4dgs_render_bwd  adjoint of the three stages above (the differentiable
  *                     pipeline of Fig. 3): replays each pixel's transmittance in
@@ -48,7 +50,7 @@
 extern "C" {
 #endif
 
-#define D4DGS_ABI_VERSION 3
+#define D4DGS_ABI_VERSION 4
 #define D4DGS_TILE 16           /* tile edge in pixels */
 #define D4DGS_CAM_REC_FLOATS 19 /* camera-stage record: p3 u3 covc6 m0_2 md2 rgb3 */
 #define D4DGS_REC_FLOATS 12     /* splat record, 3 x float4 per Gaussian */
@@ -189,11 +191,19 @@ typedef struct {
 int32_t d4dgs_abi_version(void);
 const char *d4dgs_last_error(void);
 
-/* Bytes of scratch d4dgs_bin_sort needs for n Gaussians, a width x height image and
- * up to max_instances tile instances.  Writes *bytes; the caller allocates them
- * (device, 256-byte aligned). */
+/* Bytes of scratch d4dgs_bin_sort and d4dgs_project_bin need for n Gaussians, a
+ * width x height image and up to max_instances tile instances.  Writes *bytes; the
+ * caller allocates them (device, 256-byte aligned). */
 d4dgs_status d4dgs_workspace_size(int32_t n, int32_t width, int32_t height, int64_t max_instances,
                                   size_t *bytes);
+
+/* Zeroes the tile counters of a workspace (same n, width, height, max_instances as its
+ * d4dgs_workspace_size), enqueued on `stream`.  d4dgs_project_bin needs them zero when
+ * it starts; every d4dgs_project_bin and d4dgs_bin_sort call leaves them zero, so a
+ * workspace needs this once, after it is allocated (or after anything else wrote it).
+ * Uses hipMemsetAsync: keep it out of captured graphs. */
+d4dgs_status d4dgs_workspace_init(void *workspace, int32_t n, int32_t width, int32_t height, int64_t max_instances,
+                                  d4dgs_stream stream);
 
 /* Camera stage (if `cache` is NULL or misses) and time stage at time t for all
  * scene Gaussians: Alg. 1 camera branch and per-timestamp steps; Eq. 9-15.  Writes
@@ -215,6 +225,17 @@ d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, fl
 d4dgs_status d4dgs_bin_sort(const d4dgs_splats *splats, int32_t n, int32_t width, int32_t height,
                             void *workspace, size_t workspace_bytes, d4dgs_bins *bins,
                             int32_t *d_status, d4dgs_stream stream);
+
+/* d4dgs_project followed by d4dgs_bin_sort at the camera's width and height, with
+ * identical outputs (splats, offsets, bins, *d_status), in fewer kernels: the
+ * projection also counts each tile's instances (the first binning pass), and the two
+ * scans run in one launch.  The workspace's tile counters must be zero when the call
+ * starts (d4dgs_workspace_init once; every call leaves them zero).  Same errors as the
+ * two calls; in addition, if the counters were not zero, *d_status is set to
+ * D4DGS_ERR_INVALID_ARG and every range is empty (no write outside the bins). */
+d4dgs_status d4dgs_project_bin(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, d4dgs_cam_cache *cache,
+                               d4dgs_splats *splats, void *workspace, size_t workspace_bytes, d4dgs_bins *bins,
+                               int32_t *d_status, d4dgs_stream stream);
 
 /* As d4dgs_bin_sort, then waits for the stream and returns D4DGS_ERR_CAPACITY on
  * overflow; *num_instances (host, may be NULL) receives the instance total. */

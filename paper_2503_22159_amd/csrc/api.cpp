@@ -155,12 +155,13 @@ d4dgs_status d4dgs_workspace_size(int32_t n, int32_t width, int32_t height, int6
     return D4DGS_OK;
 }
 
-d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, d4dgs_cam_cache *cache,
-                           d4dgs_splats *splats, d4dgs_stream stream) {
-    D4_TRY(check_scene(scene));
-    D4_TRY(check_camera(cam));
-    D4_TRY(check_splats(splats, scene->n));
-    if (!std::isfinite(t)) return fail(D4DGS_ERR_INVALID_ARG, "t not finite");
+}  // extern "C"
+
+namespace {
+
+// d4dgs_project, and with `bin` the projection that also runs the binning's count pass
+d4dgs_status project_impl(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, d4dgs_cam_cache *cache,
+                          d4dgs_splats *splats, d4dgs_stream stream, const BinK *bin) {
     const SceneK sk = make_scenek(*scene);
     const CamK ck = make_camk(*cam);
     int mode = 0;
@@ -183,7 +184,8 @@ d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, fl
         }
     }
     const hipError_t e = launch_project(sk, ck, t, mode, crec, ccap, (float4 *)splats->rec, splats->count,
-                                        splats->partial, (float2 *)splats->mdot, splats->motion, (hipStream_t)stream);
+                                        splats->partial, (float2 *)splats->mdot, splats->motion, (hipStream_t)stream,
+                                        bin);
     if (e != hipSuccess) {
         if (cache) cache->valid = 0;
         return hip_status(e, "d4dgs_project");
@@ -198,22 +200,71 @@ d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, fl
     return D4DGS_OK;
 }
 
-d4dgs_status d4dgs_bin_sort(const d4dgs_splats *splats, int32_t n, int32_t width, int32_t height, void *workspace,
-                            size_t workspace_bytes, d4dgs_bins *bins, int32_t *d_status, d4dgs_stream stream) {
+// checks of a binning call: sizes, bins and workspace; the workspace's layout
+d4dgs_status check_binning(const d4dgs_splats *splats, int32_t n, int32_t width, int32_t height, void *workspace,
+                           size_t workspace_bytes, const d4dgs_bins *bins, CamK &ck, SortWs &ws) {
     if (n < 0) return fail(D4DGS_ERR_INVALID_ARG, "n < 0");
     D4_TRY(check_splats(splats, n));
     D4_TRY(check_bins(bins));
-    if (!image_size_ok(width, height))
-        return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
+    if (!image_size_ok(width, height)) return fail(D4DGS_ERR_INVALID_ARG, "image size out of range");
     if (!workspace) return fail(D4DGS_ERR_INVALID_ARG, "workspace is NULL");
     d4dgs_camera dummy;
     std::memset(&dummy, 0, sizeof(dummy));
     dummy.width = width;
     dummy.height = height;
-    const CamK ck = make_camk(dummy);
+    ck = make_camk(dummy);
     if (workspace_bytes < sort_workspace_bytes(n, bins->capacity, ck.TX * ck.TY))
         return fail(D4DGS_ERR_OUT_OF_MEMORY, "workspace smaller than d4dgs_workspace_size");
-    const SortWs ws = carve_workspace(workspace, n, bins->capacity, ck.TX * ck.TY);
+    ws = carve_workspace(workspace, n, bins->capacity, ck.TX * ck.TY);
+    return D4DGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, d4dgs_cam_cache *cache,
+                           d4dgs_splats *splats, d4dgs_stream stream) {
+    D4_TRY(check_scene(scene));
+    D4_TRY(check_camera(cam));
+    D4_TRY(check_splats(splats, scene->n));
+    if (!std::isfinite(t)) return fail(D4DGS_ERR_INVALID_ARG, "t not finite");
+    return project_impl(scene, cam, t, cache, splats, stream, nullptr);
+}
+
+d4dgs_status d4dgs_workspace_init(void *workspace, int32_t n, int32_t width, int32_t height, int64_t max_instances,
+                                  d4dgs_stream stream) {
+    if (!workspace) return fail(D4DGS_ERR_INVALID_ARG, "workspace is NULL");
+    if (n < 0 || !image_size_ok(width, height) || max_instances < 1 || max_instances > (int64_t)0x7fffffff)
+        return fail(D4DGS_ERR_INVALID_ARG, "workspace sizes out of range");
+    const int tiles = ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+    return hip_status(clear_bin_counters(carve_workspace(workspace, n, max_instances, tiles), (hipStream_t)stream),
+                      "d4dgs_workspace_init");
+}
+
+d4dgs_status d4dgs_project_bin(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, d4dgs_cam_cache *cache,
+                               d4dgs_splats *splats, void *workspace, size_t workspace_bytes, d4dgs_bins *bins,
+                               int32_t *d_status, d4dgs_stream stream) {
+    D4_TRY(check_scene(scene));
+    D4_TRY(check_camera(cam));
+    if (!std::isfinite(t)) return fail(D4DGS_ERR_INVALID_ARG, "t not finite");
+    CamK ck;
+    SortWs ws;
+    D4_TRY(check_binning(splats, scene->n, cam->width, cam->height, workspace, workspace_bytes, bins, ck, ws));
+    const BinK bk = {ws.cnt_g, ws.cnt_n, ws.grp_off, ck.TX};
+    D4_TRY(project_impl(scene, cam, t, cache, splats, stream, &bk));
+    const hipError_t e = launch_bin_counted((const float4 *)splats->rec, splats->count, splats->offset,
+                                            splats->partial, scene->n, ck, ws, bins->keys, bins->values,
+                                            bins->ranges, bins->num_instances, bins->capacity, d_status,
+                                            bins->order, (hipStream_t)stream);
+    return hip_status(e, "d4dgs_project_bin");
+}
+
+d4dgs_status d4dgs_bin_sort(const d4dgs_splats *splats, int32_t n, int32_t width, int32_t height, void *workspace,
+                            size_t workspace_bytes, d4dgs_bins *bins, int32_t *d_status, d4dgs_stream stream) {
+    CamK ck;
+    SortWs ws;
+    D4_TRY(check_binning(splats, n, width, height, workspace, workspace_bytes, bins, ck, ws));
     const hipError_t e = launch_bin_sort((const float4 *)splats->rec, splats->count, splats->offset, splats->partial,
                                          n, ck, ws, bins->keys, bins->values, bins->ranges, bins->num_instances,
                                          bins->capacity, d_status, bins->order, (hipStream_t)stream);
@@ -234,6 +285,8 @@ d4dgs_status d4dgs_bin_sort_sync(const d4dgs_splats *splats, int32_t n, int32_t 
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     D4_TRY(hip_status(e, "d4dgs_bin_sort_sync"));
     if (num_instances) *num_instances = total;
+    if (misc[1] == (uint32_t)D4DGS_ERR_INVALID_ARG)
+        return fail(D4DGS_ERR_INVALID_ARG, "workspace tile counters were not zero (see d4dgs_workspace_init)");
     if (misc[1] == (uint32_t)D4DGS_ERR_CAPACITY)
         return fail(D4DGS_ERR_CAPACITY, "tile instances (" + std::to_string(total) + ") exceed capacity (" +
                                             std::to_string(bins->capacity) + ")");

@@ -2,19 +2,19 @@
 // that the paper renders with, Sec. 3.2.2), designed for MI355X:
 //
 //   k_scan_partials  one block: exclusive scan of the per-block count sums written by
-//                    the projection; instance total; capacity check; clears the tile
-//                    counters.
-//   k_emit<COUNT>    per block of 256 Gaussians.  COUNT pass: per-Gaussian offsets
-//                    (block scan) and one L2 atomic increment per instance on its tile's
-//                    counter.  SCATTER pass: every instance takes the next free position
-//                    of its tile's bucket (atomic cursor) and stores the 64-bit sort key
-//                    (float-bits(depth) << 32) | gaussian.  Instances are enumerated by
-//                    the whole wave (lane j takes instance j of the wave's 64 Gaussians,
-//                    owner found by binary search over the wave prefix), so splats with
-//                    large rectangles do not stall a wave.
-//   k_tile_scan      one block: exclusive scan over tiles -> ranges, bucket cursors.
-//                    (With a tile order, the scatter pass has one more workgroup, which
-//                    sorts the tiles by list length for the launches that follow.)
+//                    the projection into block offsets; instance total; capacity check;
+//                    clears the tile counters.
+//   k_count          count pass per block of 256 Gaussians (emit.hpp): grouped
+//                    reservations per (block, tile), or ungrouped increments.  The
+//                    projection can do this pass itself (launch_bin_counted then follows).
+//   k_tile_scan      one block: exclusive scan over tiles -> ranges and the ungrouped
+//                    cursors; leaves the counters zero.  k_scan_both: both scans in one
+//                    block, after a projection that counted.
+//   k_scatter        per block: per-Gaussian offsets (block offset + block scan), then
+//                    every instance's 64-bit sort key (float-bits(depth) << 32) | gaussian
+//                    at its position in the tile's bucket.  (With a tile order, one more
+//                    workgroup sorts the tiles by list length for the launches that
+//                    follow.)
 //   k_tile_sort      one workgroup of 256 per tile sorts its bucket by the 64-bit key --
 //                    depth, ties by Gaussian index: a unique order, so the result does not
 //                    depend on the order the atomics handed out positions.  Buckets of up to
@@ -29,7 +29,7 @@
 //
 // The instance total lives on the device; no host synchronisation is needed.  If it
 // exceeds the capacity, a status word is set and every later stage does nothing.
-#include "internal.hpp"
+#include "emit.hpp"
 
 namespace d4 {
 
@@ -52,15 +52,15 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *tm
     return base + inc - v;
 }
 
-// misc[0] = instance total (0 on overflow), misc[1] = status (0 or CAPACITY)
-__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t *__restrict__ partial, int nb,
-                                                               int64_t capacity, int64_t *__restrict__ num_inst,
-                                                               uint32_t *__restrict__ misc,
-                                                               int32_t *__restrict__ d_status,
-                                                               uint32_t *__restrict__ tcnt, int tiles) {
-    __shared__ uint64_t wsum[kScanThreads / kWave];
+// Scan of the per-block count sums written by the projection into block offsets (in
+// place); instance total and capacity check.  misc[0] = instance total (0 on overflow),
+// misc[1] = status (0 or CAPACITY).  Returns whether the total exceeds the capacity;
+// *total_out receives the total (every thread).
+__device__ __forceinline__ bool scan_block_sums(uint32_t *__restrict__ partial, int nb, int64_t capacity,
+                                                int64_t *__restrict__ num_inst, uint32_t *__restrict__ misc,
+                                                int32_t *__restrict__ d_status, uint64_t *wsum,
+                                                uint64_t *total_out) {
     const int tid = threadIdx.x;
-    for (int i = tid; i < tiles; i += kScanThreads) tcnt[i] = 0u;
     const int per = (nb + kScanThreads - 1) / kScanThreads;
     const int b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
     uint64_t s = 0;
@@ -84,29 +84,104 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t *__rest
         partial[i] = (uint32_t)min(run, (uint64_t)0xffffffffull);
         run += v;
     }
+    const bool over = total > (uint64_t)capacity;
+    *total_out = total;
     if (tid == 0) {
-        const bool over = total > (uint64_t)capacity;
         *num_inst = (int64_t)total;
         misc[0] = (uint32_t)(over ? 0ull : total);
         misc[1] = over ? (uint32_t)D4DGS_ERR_CAPACITY : 0u;
         if (d_status && over) *d_status = D4DGS_ERR_CAPACITY;
     }
+    return over;
 }
 
-// Emission of tile instances, in two passes over each block of 256 Gaussians.
-//
-// RESERVE: per-Gaussian offsets (block scan), then every instance gets a position inside
-//   its tile's bucket, relative to the bucket start.  Device-scope atomics are expensive
-//   on this part, so they are aggregated: when the block's splats together cover at most
-//   kCells tiles (a spatially coherent block), instances are counted in LDS and one
-//   global atomic per (block, tile) reserves the group's range (stored in grp_off);
-//   otherwise each instance reserves its own slot (stored in inst_off, indexed by its
-//   emission position).
-// SCATTER (after the tile scan): recomputes the same enumeration, takes a rank inside its
-//   group from an LDS counter (any unique rank will do -- the per-tile sort fixes the
-//   final order) and writes its key to bucket[tile start + reserved offset].  No global
-//   atomics.
-constexpr int kCells = 2048;
+// Exclusive scan of the tile counts (grouped + ungrouped) into ranges and the ungrouped
+// cursors (start + grouped count); the counters are left zero for the next frame.
+// Ranges are empty on overflow, and also when the tile counts do not add up to the
+// instance total `expect` (counters that were not zero when the count pass started: a
+// workspace that was not initialised); then misc and *d_status report INVALID_ARG.
+__device__ __forceinline__ void scan_tiles(uint32_t *__restrict__ cnt_g, uint32_t *__restrict__ cnt_n,
+                                           uint32_t *__restrict__ cur_n, int tiles, uint32_t *__restrict__ ranges,
+                                           bool over, uint64_t expect, uint32_t *__restrict__ misc,
+                                           int32_t *__restrict__ d_status, uint32_t *wsum) {
+    const int tid = threadIdx.x;
+    const int per = (tiles + kScanThreads - 1) / kScanThreads;
+    const int i0 = min(tiles, tid * per), i1 = min(tiles, i0 + per);
+    uint64_t s64 = 0;
+    for (int i = i0; i < i1; ++i) s64 += over ? 0u : (uint64_t)cnt_g[i] + cnt_n[i];
+    const uint32_t s = (uint32_t)min(s64, (uint64_t)0xffffffffull);
+    const uint32_t inc = wave_incl_scan(s);
+    if (lane_id() == kWave - 1) wsum[tid / kWave] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+    uint64_t total = 0;
+    for (int i = 0; i < kScanThreads / kWave; ++i) {
+        base += (i < tid / kWave) ? wsum[i] : 0u;
+        total += wsum[i];
+    }
+    const bool bad = !over && (s64 != s || total != expect);
+    const bool empty = over || __syncthreads_or(bad);
+    if (tid == 0 && empty && !over) {
+        misc[0] = 0u;
+        misc[1] = (uint32_t)D4DGS_ERR_INVALID_ARG;
+        if (d_status) *d_status = D4DGS_ERR_INVALID_ARG;
+    }
+    uint32_t run = empty ? 0u : base + inc - s;
+    for (int i = i0; i < i1; ++i) {
+        const uint32_t g = cnt_g[i], c = empty ? 0u : g + cnt_n[i];
+        ranges[2 * i] = run;
+        ranges[2 * i + 1] = run + c;
+        cur_n[i] = run + g;
+        cnt_g[i] = 0u;
+        cnt_n[i] = 0u;
+        run += c;
+    }
+}
+
+// The two scans as separate kernels (binning after a plain projection): the first also
+// clears the tile counters, so that a workspace needs no initialisation.
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t *__restrict__ partial, int nb,
+                                                               int64_t capacity, int64_t *__restrict__ num_inst,
+                                                               uint32_t *__restrict__ misc,
+                                                               int32_t *__restrict__ d_status,
+                                                               uint32_t *__restrict__ cnt_g,
+                                                               uint32_t *__restrict__ cnt_n, int tiles) {
+    __shared__ uint64_t wsum[kScanThreads / kWave];
+    for (int i = threadIdx.x; i < tiles; i += kScanThreads) {
+        cnt_g[i] = 0u;
+        cnt_n[i] = 0u;
+    }
+    uint64_t total;
+    scan_block_sums(partial, nb, capacity, num_inst, misc, d_status, wsum, &total);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict__ cnt_g, uint32_t *__restrict__ cnt_n,
+                                                           uint32_t *__restrict__ cur_n, int tiles,
+                                                           uint32_t *__restrict__ ranges, uint32_t *__restrict__ misc,
+                                                           int32_t *__restrict__ d_status) {
+    __shared__ uint32_t wsum[kScanThreads / kWave];
+    const bool over = misc[1] != 0u;
+    const uint64_t expect = misc[0];
+    __syncthreads();  // every thread has read misc before thread 0 may rewrite it
+    scan_tiles(cnt_g, cnt_n, cur_n, tiles, ranges, over, expect, misc, d_status, wsum);
+}
+
+// Both scans in one workgroup, after the projection that counted the instances (its
+// counters started at zero, as every scan leaves them).
+__global__ __launch_bounds__(kScanThreads) void k_scan_both(uint32_t *__restrict__ partial, int nb, int64_t capacity,
+                                                           int64_t *__restrict__ num_inst,
+                                                           uint32_t *__restrict__ misc,
+                                                           int32_t *__restrict__ d_status,
+                                                           uint32_t *__restrict__ cnt_g,
+                                                           uint32_t *__restrict__ cnt_n,
+                                                           uint32_t *__restrict__ cur_n, int tiles,
+                                                           uint32_t *__restrict__ ranges) {
+    __shared__ uint64_t wsum64[kScanThreads / kWave];
+    __shared__ uint32_t wsum32[kScanThreads / kWave];
+    uint64_t total;
+    const bool over = scan_block_sums(partial, nb, capacity, num_inst, misc, d_status, wsum64, &total);
+    scan_tiles(cnt_g, cnt_n, cur_n, tiles, ranges, over, total, misc, d_status, wsum32);
+}
 
 // Tile order of the per-tile launches (see tile_unit): the tiles of row class x (rows
 // x, x + 8, ...: the tiles XCD x takes) form the x-th segment of the order, and inside a
@@ -167,139 +242,65 @@ __device__ void build_tile_order(const uint32_t *__restrict__ ranges, int tiles,
 }
 
 
-template <bool RESERVE>
-__global__ __launch_bounds__(kBlock) void k_emit(const float4 *__restrict__ rec, const uint32_t *__restrict__ count,
-                                                 const uint32_t *__restrict__ partial, uint32_t *__restrict__ offset,
-                                                 int n, int TX, const uint32_t *__restrict__ misc,
-                                                 uint32_t *__restrict__ tcnt, uint32_t *__restrict__ grp_off,
-                                                 uint32_t *__restrict__ inst_off, uint64_t *__restrict__ bucket,
-                                                 const uint32_t *__restrict__ ranges, int tiles,
-                                                 uint32_t *__restrict__ order) {
-    static_assert(kCells >= kOrderKeys, "the tile order's histogram lives in s_cell");
-    __shared__ uint32_t tmp4[kBlock / kWave];
-    __shared__ uint32_t s_incl[kBlock];
-    __shared__ uint32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock], s_dbits[kBlock];
-    __shared__ uint32_t s_cell[kCells];
-    __shared__ uint32_t s_box[4][kBlock / kWave];
-    // with a tile order the scatter pass has one extra workgroup, the first one (so that
-    // it starts first), which builds the order (also on overflow: the blends read it)
-    const int blk = (int)blockIdx.x - ((!RESERVE && order) ? 1 : 0);
-    if (blk < 0) {
-        build_tile_order(ranges, tiles, TX, order, s_cell, tmp4);
-        return;
-    }
-    if (misc[1] != 0u) return;  // capacity exceeded: nothing downstream runs
-    const int tid = threadIdx.x, gi = blk * kBlock + tid, wv = tid / kWave;
+// Count pass over a block of 256 projected splats (binning after a plain projection).
+__global__ __launch_bounds__(kBlock) void k_count(const float4 *__restrict__ rec, const uint32_t *__restrict__ count,
+                                                  int n, int TX, uint32_t *__restrict__ cnt_g,
+                                                  uint32_t *__restrict__ cnt_n, uint32_t *__restrict__ grp_off) {
+    __shared__ EmitLds L;
+    const int gi = blockIdx.x * kBlock + threadIdx.x;
     const uint32_t cnt = gi < n ? count[gi] : 0u;
-    const uint32_t excl = block_excl_scan_256(cnt, tmp4);
-    const uint32_t boff = partial[blk];
-    if (RESERVE && gi < n) offset[gi] = boff + excl;
-    s_incl[tid] = wave_incl_scan(cnt);
-    uint32_t bx0 = 0xffffu, by0 = 0xffffu, bx1 = 0u, by1 = 0u;
+    uint32_t lo = 0u, hi = 0u;
     if (cnt) {
         const float4 r2 = rec[3 * (size_t)gi + 2];
-        const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
-        bx0 = lo & 0xffffu;
-        by0 = lo >> 16;
-        bx1 = hi & 0xffffu;
-        by1 = hi >> 16;
-        s_x0[tid] = bx0;
-        s_y0[tid] = by0;
-        s_w[tid] = bx1 - bx0;
-        s_dbits[tid] = __float_as_uint(r2.y);
+        lo = __float_as_uint(r2.z);
+        hi = __float_as_uint(r2.w);
     }
-    // union rectangle of the block's splats
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        bx0 = min(bx0, (uint32_t)__shfl_xor((int)bx0, o, kWave));
-        by0 = min(by0, (uint32_t)__shfl_xor((int)by0, o, kWave));
-        bx1 = max(bx1, (uint32_t)__shfl_xor((int)bx1, o, kWave));
-        by1 = max(by1, (uint32_t)__shfl_xor((int)by1, o, kWave));
-    }
-    if (lane_id() == 0) {
-        s_box[0][wv] = bx0;
-        s_box[1][wv] = by0;
-        s_box[2][wv] = bx1;
-        s_box[3][wv] = by1;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kBlock / kWave; ++i) {
-        bx0 = min(bx0, s_box[0][i]);
-        by0 = min(by0, s_box[1][i]);
-        bx1 = max(bx1, s_box[2][i]);
-        by1 = max(by1, s_box[3][i]);
-    }
-    const uint32_t uw = bx1 > bx0 ? bx1 - bx0 : 0u, uh = by1 > by0 ? by1 - by0 : 0u;
-    const bool grouped = uw * uh <= (uint32_t)kCells;
-    if (grouped)
-        for (uint32_t c = tid; c < uw * uh; c += kBlock) s_cell[c] = 0u;
-    __syncthreads();
-    const int wbase = wv * kWave;
-    const uint32_t wtotal = s_incl[wbase + kWave - 1];
-    const uint32_t wstart = boff + __shfl(excl, 0, kWave);  // emission position of the wave's first instance
-    for (uint32_t j = lane_id(); j < wtotal; j += kWave) {
-        int lo = 0, hi = kWave - 1;  // owner: first lane whose inclusive prefix exceeds j
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_incl[wbase + mid] > j) hi = mid; else lo = mid + 1;
-        }
-        const int o = wbase + lo;
-        const uint32_t kk = j - (lo > 0 ? s_incl[o - 1] : 0u);
-        const uint32_t w = s_w[o];
-        const uint32_t tyy = s_y0[o] + kk / w, txx = s_x0[o] + kk % w;
-        const uint32_t tile = tyy * (uint32_t)TX + txx;
-        const uint32_t cell = (tyy - by0) * uw + (txx - bx0);
-        if (RESERVE) {
-            if (grouped)
-                atomicAdd(&s_cell[cell], 1u);
-            else
-                inst_off[wstart + j] = atomicAdd(&tcnt[tile], 1u);
-        } else {
-            uint32_t pos;
-            if (grouped)
-                pos = tcnt[tile] + grp_off[(size_t)blk * kCells + cell] + atomicAdd(&s_cell[cell], 1u);
-            else
-                pos = tcnt[tile] + inst_off[wstart + j];
-            bucket[pos] = ((uint64_t)s_dbits[o] << 32) | (uint32_t)(blk * kBlock + o);
-        }
-    }
-    if (RESERVE && grouped) {
-        __syncthreads();
-        for (uint32_t c = tid; c < uw * uh; c += kBlock) {
-            const uint32_t k = s_cell[c];
-            if (k) {
-                const uint32_t tile = (by0 + c / uw) * (uint32_t)TX + (bx0 + c % uw);
-                grp_off[(size_t)blk * kCells + c] = atomicAdd(&tcnt[tile], k);
-            }
-        }
-    }
+    emit_count(L, cnt, lo, hi, TX, blockIdx.x, cnt_g, cnt_n, grp_off);
 }
 
-// Exclusive scan of the tile counts: ranges and the scatter cursors (tcnt := start).
-__global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict__ tcnt, int tiles,
-                                                           uint32_t *__restrict__ ranges,
-                                                           const uint32_t *__restrict__ misc) {
-    __shared__ uint32_t wsum[kScanThreads / kWave];
-    const int tid = threadIdx.x;
-    const bool over = misc[1] != 0u;
-    const int per = (tiles + kScanThreads - 1) / kScanThreads;
-    const int i0 = min(tiles, tid * per), i1 = min(tiles, i0 + per);
-    uint32_t s = 0;
-    for (int i = i0; i < i1; ++i) s += tcnt[i];
-    const uint32_t inc = wave_incl_scan(s);
-    if (lane_id() == kWave - 1) wsum[tid / kWave] = inc;
-    __syncthreads();
-    uint32_t base = 0;
-    for (int i = 0; i < tid / kWave; ++i) base += wsum[i];
-    uint32_t run = base + inc - s;
-    for (int i = i0; i < i1; ++i) {
-        const uint32_t c = over ? 0u : tcnt[i];
-        ranges[2 * i] = run;
-        ranges[2 * i + 1] = run + c;
-        tcnt[i] = run;
-        run += c;
+// Scatter pass, after the scans: per-Gaussian offsets (block offset + block scan), then
+// every instance's 64-bit sort key (float-bits(depth) << 32) | gaussian at its position
+// in the tile's bucket.  With a tile order the launch has one extra workgroup, the
+// first (so that it starts first), which builds the order (also on overflow: the
+// blends read it).
+__global__ __launch_bounds__(kBlock) void k_scatter(const float4 *__restrict__ rec, const uint32_t *__restrict__ count,
+                                                    const uint32_t *__restrict__ partial,
+                                                    uint32_t *__restrict__ offset, int n, int TX,
+                                                    const uint32_t *__restrict__ misc,
+                                                    const uint32_t *__restrict__ grp_off,
+                                                    uint32_t *__restrict__ cur_n, uint64_t *__restrict__ bucket,
+                                                    const uint32_t *__restrict__ ranges, int tiles,
+                                                    uint32_t *__restrict__ order) {
+    static_assert(kCells >= kOrderKeys, "the tile order's histogram lives in the cell array");
+    __shared__ EmitLds L;
+    __shared__ uint32_t tmp4[kBlock / kWave];
+    __shared__ uint32_t s_dbits[kBlock];
+    const int blk = (int)blockIdx.x - (order ? 1 : 0);
+    if (blk < 0) {
+        build_tile_order(ranges, tiles, TX, order, L.cell, tmp4);
+        return;
     }
+    if (misc[1] != 0u) return;  // capacity exceeded (or a bad workspace): nothing downstream runs
+    const uint32_t total = misc[0];
+    const int tid = threadIdx.x, gi = blk * kBlock + tid;
+    const uint32_t cnt = gi < n ? count[gi] : 0u;
+    const uint32_t excl = block_excl_scan_256(cnt, tmp4);
+    if (gi < n) offset[gi] = partial[blk] + excl;
+    uint32_t lo = 0u, hi = 0u;
+    if (cnt) {
+        const float4 r2 = rec[3 * (size_t)gi + 2];
+        lo = __float_as_uint(r2.z);
+        hi = __float_as_uint(r2.w);
+        s_dbits[tid] = __float_as_uint(r2.y);
+    }
+    const EmitBox B = emit_box(L, cnt, lo, hi);
+    emit_each(L, B, TX, [&](int o, uint32_t tile, uint32_t cell) {
+        const uint32_t pos = B.grouped ? ranges[2 * tile] + grp_off[(size_t)blk * kCells + cell] +
+                                             atomicAdd(&L.cell[cell], 1u)
+                                       : atomicAdd(&cur_n[tile], 1u);
+        if (pos < total)  // always, when the counters started at zero; a guard for the bucket otherwise
+            bucket[pos] = ((uint64_t)s_dbits[o] << 32) | (uint32_t)(blk * kBlock + o);
+    });
 }
 
 __device__ __forceinline__ void write_out(uint64_t k, uint32_t pos, uint32_t tile, uint64_t *__restrict__ keys,
@@ -443,33 +444,61 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-// workspace: bucket keys [cap] u64, alt keys [cap] u64 (its first half doubles as the
-// per-instance reservations of the emission, which are dead before the tile sort runs),
-// group reservations [blocks][kCells] u32, tile counters [tiles], misc [64]
+// workspace: bucket keys [cap] u64, alt keys [cap] u64 (the large-bucket radix sort's
+// scratch), group reservations [blocks][kCells] u32, grouped and ungrouped tile counters
+// and ungrouped cursors [tiles] u32 each, misc [64] u32
 size_t sort_workspace_bytes(int n, int64_t capacity, int tiles) {
     const int64_t cap = capacity > 0 ? capacity : 1;
     const size_t nb = (size_t)((n > 0 ? n : 1) + kBlock - 1) / kBlock;
-    return align256(cap * 8) * 2 + align256(nb * kCells * 4) + align256((size_t)(tiles > 0 ? tiles : 1) * 4) +
-           align256(64 * 4);
+    const size_t tb = align256((size_t)(tiles > 0 ? tiles : 1) * 4);
+    return align256(cap * 8) * 2 + align256(nb * kCells * 4) + 3 * tb + align256(64 * 4);
 }
 
 SortWs carve_workspace(void *ws, int n, int64_t capacity, int tiles) {
     const int64_t cap = capacity > 0 ? capacity : 1;
     const size_t nb = (size_t)((n > 0 ? n : 1) + kBlock - 1) / kBlock;
+    const size_t tb = align256((size_t)(tiles > 0 ? tiles : 1) * 4);
     SortWs w;
     char *p = (char *)ws;
     w.bucket = (uint64_t *)p;
     p += align256(cap * 8);
     w.alt = (uint64_t *)p;
-    w.inst_off = (uint32_t *)p;
     p += align256(cap * 8);
     w.grp_off = (uint32_t *)p;
     p += align256(nb * kCells * 4);
-    w.tcnt = (uint32_t *)p;
-    p += align256((size_t)(tiles > 0 ? tiles : 1) * 4);
+    w.cnt_g = (uint32_t *)p;
+    p += tb;
+    w.cnt_n = (uint32_t *)p;
+    p += tb;
+    w.cur_n = (uint32_t *)p;
+    p += tb;
     w.misc = (uint32_t *)p;
+    w.counter_bytes = 2 * tb;
     return w;
 }
+
+hipError_t clear_bin_counters(const SortWs &ws, hipStream_t st) {
+    return hipMemsetAsync(ws.cnt_g, 0, ws.counter_bytes, st);  // cnt_g and cnt_n, adjacent
+}
+
+namespace {
+
+// the passes after the count: scatter (with the tile order's extra workgroup) and sort
+void launch_scatter_sort(const float4 *rec, const uint32_t *count, uint32_t *offset, const uint32_t *partial, int n,
+                         const CamK &c, const SortWs &ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
+                         uint32_t *order, hipStream_t st) {
+    const int tiles = c.TX * c.TY;
+    const int nb = (n + kBlock - 1) / kBlock;
+    if (nb > 0 || order)
+        hipLaunchKernelGGL(k_scatter, dim3(nb + (order ? 1 : 0)), dim3(kBlock), 0, st, rec, count, partial, offset, n,
+                           c.TX, (const uint32_t *)ws.misc, (const uint32_t *)ws.grp_off, ws.cur_n, ws.bucket,
+                           (const uint32_t *)ranges, tiles, order);
+    hipLaunchKernelGGL(k_tile_sort, dim3(tile_grid(c.TX, c.TY, 1)), dim3(kSortThreads), 0, st,
+                       (const uint64_t *)ws.bucket, ws.alt, ranges, tiles, keys, vals, ws.misc,
+                       (const uint32_t *)order, c.TX, c.TY);
+}
+
+}  // namespace
 
 hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *offset, uint32_t *partial, int n,
                            const CamK &c, const SortWs &ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
@@ -478,20 +507,24 @@ hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *o
     const int tiles = c.TX * c.TY;
     const int nb = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partial, nb, capacity, num_inst,
-                       ws.misc, d_status, ws.tcnt, tiles);
+                       ws.misc, d_status, ws.cnt_g, ws.cnt_n, tiles);
     if (nb > 0)
-        hipLaunchKernelGGL(k_emit<true>, dim3(nb), dim3(kBlock), 0, st, rec, count, partial, offset, n, c.TX,
-                           ws.misc, ws.tcnt, ws.grp_off, ws.inst_off, ws.bucket, (const uint32_t *)nullptr, tiles,
-                           (uint32_t *)nullptr);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanThreads), 0, st, ws.tcnt, tiles, ranges, ws.misc);
-    // scatter; with a tile order one more workgroup (the first) builds it
-    if (nb > 0 || order)
-        hipLaunchKernelGGL(k_emit<false>, dim3(nb + (order ? 1 : 0)), dim3(kBlock), 0, st, rec, count, partial,
-                           offset, n, c.TX, ws.misc, ws.tcnt, ws.grp_off, ws.inst_off, ws.bucket,
-                           (const uint32_t *)ranges, tiles, order);
-    hipLaunchKernelGGL(k_tile_sort, dim3(tile_grid(c.TX, c.TY, 1)), dim3(kSortThreads), 0, st,
-                       (const uint64_t *)ws.bucket, ws.alt, ranges, tiles, keys, vals, ws.misc,
-                       (const uint32_t *)order, c.TX, c.TY);
+        hipLaunchKernelGGL(k_count, dim3(nb), dim3(kBlock), 0, st, rec, count, n, c.TX, ws.cnt_g, ws.cnt_n,
+                           ws.grp_off);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanThreads), 0, st, ws.cnt_g, ws.cnt_n, ws.cur_n, tiles, ranges,
+                       ws.misc, d_status);
+    launch_scatter_sort(rec, count, offset, partial, n, c, ws, keys, vals, ranges, order, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_counted(const float4 *rec, const uint32_t *count, uint32_t *offset, uint32_t *partial, int n,
+                              const CamK &c, const SortWs &ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
+                              int64_t *num_inst, int64_t capacity, int32_t *d_status, uint32_t *order,
+                              hipStream_t st) {
+    const int nb = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_scan_both, dim3(1), dim3(kScanThreads), 0, st, partial, nb, capacity, num_inst, ws.misc,
+                       d_status, ws.cnt_g, ws.cnt_n, ws.cur_n, c.TX * c.TY, ranges);
+    launch_scatter_sort(rec, count, offset, partial, n, c, ws, keys, vals, ranges, order, st);
     return hipGetLastError();
 }
 

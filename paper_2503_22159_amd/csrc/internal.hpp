@@ -205,10 +205,18 @@ struct SceneK {
 
 SceneK make_scenek(const d4dgs_scene &s);
 
+// Where a projection that also runs the binning's count pass writes (the counters of a
+// workspace; they must be zero when the projection starts).
+struct BinK {
+    uint32_t *cnt_g, *cnt_n, *grp_off;
+    int TX;
+};
+
 // mode 0: camera + time stage, no record; 1: camera + time stage, writes record; 2: time stage from record
+// bin (optional): also run the binning's count pass (see BinK)
 hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, float *cam_rec, int cam_cap,
                           float4 *rec, uint32_t *count, uint32_t *block_sums, float2 *mdot, int motion,
-                          hipStream_t st);
+                          hipStream_t st, const BinK *bin = nullptr);
 
 // One request of a batched projection (kernel argument, by value).
 struct ReqK {
@@ -243,22 +251,34 @@ hipError_t launch_project_times(const SceneK &s, const CamK &c, int mode, float 
                                 const TimesArgs &args, hipStream_t st);
 
 struct SortWs {
-    uint64_t *bucket;    // [capacity] per-tile buckets of (depth bits << 32 | gaussian)
-    uint64_t *alt;       // [capacity] scratch of the large-bucket radix sort
-    uint32_t *inst_off;  // [capacity] per-instance bucket reservations (aliases alt)
-    uint32_t *grp_off;   // [blocks][kCells] per-(block, tile) bucket reservations
-    uint32_t *tcnt;    // [tiles] tile counters, then bucket cursors
-    uint32_t *misc;    // [64]: [0] instances kept, [1] status
+    uint64_t *bucket;   // [capacity] per-tile buckets of (depth bits << 32 | gaussian)
+    uint64_t *alt;      // [capacity] scratch of the large-bucket radix sort
+    uint32_t *grp_off;  // [blocks][kCells] per-(block, tile) bucket reservations
+    uint32_t *cnt_g;    // [tiles] grouped instance counters (zero between calls)
+    uint32_t *cnt_n;    // [tiles] ungrouped instance counters (zero between calls)
+    uint32_t *cur_n;    // [tiles] ungrouped bucket cursors
+    uint32_t *misc;     // [64]: [0] instances kept, [1] status
+    size_t counter_bytes;  // bytes from cnt_g to the end of cnt_n
 };
 
 size_t sort_workspace_bytes(int n, int64_t capacity, int tiles);
 SortWs carve_workspace(void *ws, int n, int64_t capacity, int tiles);
+
+// zeroes a workspace's tile counters (which every binning leaves zero)
+hipError_t clear_bin_counters(const SortWs &ws, hipStream_t st);
 
 // order (optional, [tiles]): receives the tiles longest list first
 hipError_t launch_bin_sort(const float4 *rec, const uint32_t *count, uint32_t *offset, uint32_t *partial, int n,
                            const CamK &c, const SortWs &ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
                            int64_t *num_inst, int64_t capacity, int32_t *d_status, uint32_t *order,
                            hipStream_t st);
+
+// The binning after a projection that counted (launch_project with a BinK): both scans
+// in one launch, the scatter and the sort; leaves the counters zero.
+hipError_t launch_bin_counted(const float4 *rec, const uint32_t *count, uint32_t *offset, uint32_t *partial, int n,
+                              const CamK &c, const SortWs &ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
+                              int64_t *num_inst, int64_t capacity, int32_t *d_status, uint32_t *order,
+                              hipStream_t st);
 
 // order (optional): the binning's tile order; e0/e1 (optional): events set to the blend
 // kernel's own start and end

@@ -13,7 +13,7 @@
 // computed with IEEE float +,-,*,/ and sqrt in the written order (compiled with
 // -ffp-contract=off; correctly rounded division and square root).  One thread per
 // Gaussian; planar loads coalesce across the wave.
-#include "internal.hpp"
+#include "emit.hpp"
 
 namespace d4 {
 
@@ -235,14 +235,16 @@ __device__ __forceinline__ void store_rec(float4 *__restrict__ rec, int gi, cons
 }
 
 // MODE 0: camera + time stage; 1: camera + time stage and store the camera record;
-// 2: time stage from a stored camera record.  Also writes each block's count sum.
-template <int MODE, int DEG>
+// 2: time stage from a stored camera record.  Also writes each block's count sum.  BIN:
+// also the binning's count pass over the block's splats (emit.hpp), from the rectangles
+// just computed.
+template <int MODE, int DEG, bool BIN>
 __global__ __launch_bounds__(kBlock) void k_project(SceneK s, CamK c, float t, float *__restrict__ cam_rec,
                                                    int cap, float4 *__restrict__ rec,
                                                    uint32_t *__restrict__ count, uint32_t *__restrict__ block_sums,
-                                                   float2 *__restrict__ mdot, int motion) {
+                                                   float2 *__restrict__ mdot, int motion, BinK bin) {
     const int gi = blockIdx.x * kBlock + threadIdx.x;
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, rlo = 0, rhi = 0;
     if (gi < s.n) {
         CamRec cr;
         bool ok;
@@ -302,11 +304,17 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneK s, CamK c, float t, f
             if (cnt) {
                 store_rec(rec, gi, r0, r1, r2);
                 if (mdot) mdot[gi] = vel;  // dm/dt at t
+                rlo = __float_as_uint(r2.z);
+                rhi = __float_as_uint(r2.w);
             }
         }
         count[gi] = cnt;
     }
     block_count_sum(cnt, block_sums);
+    if (BIN) {
+        __shared__ EmitLds L;
+        emit_count(L, cnt, rlo, rhi, bin.TX, blockIdx.x, bin.cnt_g, bin.cnt_n, bin.grp_off);
+    }
 }
 
 // Batched projection for the server: one thread per Gaussian loads its parameters and
@@ -426,12 +434,19 @@ __global__ __launch_bounds__(kBlock) void k_project_times(SceneK s, CamK c, floa
 
 hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, float *cam_rec, int cam_cap,
                           float4 *rec, uint32_t *count, uint32_t *block_sums, float2 *mdot, int motion,
-                          hipStream_t st) {
+                          hipStream_t st, const BinK *bin) {
     if (s.n == 0) return hipSuccess;
     const int grid = (s.n + kBlock - 1) / kBlock;
-#define D4_LAUNCH(M, D)                                                                                  \
-    hipLaunchKernelGGL((k_project<M, D>), dim3(grid), dim3(kBlock), 0, st, s, c, t, cam_rec, cam_cap, rec, \
-                       count, block_sums, mdot, motion)
+    const BinK nobin = {nullptr, nullptr, nullptr, 0};
+#define D4_LAUNCH(M, D)                                                                                        \
+    do {                                                                                                       \
+        if (bin)                                                                                               \
+            hipLaunchKernelGGL((k_project<M, D, true>), dim3(grid), dim3(kBlock), 0, st, s, c, t, cam_rec,     \
+                               cam_cap, rec, count, block_sums, mdot, motion, *bin);                           \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_project<M, D, false>), dim3(grid), dim3(kBlock), 0, st, s, c, t, cam_rec,    \
+                               cam_cap, rec, count, block_sums, mdot, motion, nobin);                          \
+    } while (0)
     if (mode == 2) {
         D4_LAUNCH(2, 0);
     } else {

@@ -346,9 +346,10 @@ def render(mean, scale, quat, opacity, t_mean, t_scale, velocity, sh, *, cam, t,
 class Renderer:
     """Fixed device buffers for repeated frames of one resolution (timing loops,
     sweeps).  Fully asynchronous: no host synchronisation per frame.  The argument
-    structs of the three entry points are built once (camera structs once per camera
-    object: cameras passed here are treated as immutable), so a frame costs three
-    foreign calls on the host."""
+    structs of the entry points are built once (camera structs once per camera
+    object: cameras passed here are treated as immutable), so a frame costs two
+    foreign calls on the host: d4dgs_project_bin (projection and binning) and the
+    blend.  project() + bin_sort() run the same stages through the separate calls."""
 
     def __init__(self, scene: DeviceScene, width, height, capacity=None, cache=True, keep_state=False,
                  tile_order=True):
@@ -374,6 +375,9 @@ class Renderer:
         self._state = (_ptr(st.final_T), _ptr(st.n_contrib)) if keep_state else (None, None)
         self._cams = {}
         self._bgs = {}
+        # the fused projection + binning needs the workspace's tile counters zero once
+        B.check(B.lib.d4dgs_workspace_init(self._ws[0], st.n, self.width, self.height, st.capacity, _stream()))
+        torch.cuda.synchronize(dev)
 
     def _cam(self, cam):
         hit = self._cams.get(id(cam))
@@ -394,6 +398,13 @@ class Renderer:
         B.check(B.lib.d4dgs_project(C.byref(self._scene_s), C.byref(self._cam(cam)), float(t), self._cache_p,
                                     C.byref(self._sp), stream or _stream()))
 
+    def project_bin(self, cam, t, stream=None):
+        """project() + bin_sort() in one call, with fewer kernels (same output)."""
+        assert cam.width == self.width and cam.height == self.height
+        B.check(B.lib.d4dgs_project_bin(C.byref(self._scene_s), C.byref(self._cam(cam)), float(t), self._cache_p,
+                                        C.byref(self._sp), self._ws[0], self._ws[1], C.byref(self._bn),
+                                        self._status, stream or _stream()))
+
     def bin_sort(self, stream=None):
         B.check(B.lib.d4dgs_bin_sort(C.byref(self._sp), self.st.n, self.width, self.height, self._ws[0],
                                      self._ws[1], C.byref(self._bn), self._status, stream or _stream()))
@@ -413,8 +424,7 @@ class Renderer:
 
     def render(self, cam, t, bg=(0.0, 0.0, 0.0)):
         stream = _stream()
-        self.project(cam, t, stream)
-        self.bin_sort(stream)
+        self.project_bin(cam, t, stream)
         return self.blend(bg, stream)
 
     def backward(self, cam, t, dL_dimg, grads, bg=(0.0, 0.0, 0.0)):
