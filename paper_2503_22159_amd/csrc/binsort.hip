@@ -95,46 +95,129 @@ __device__ __forceinline__ bool scan_block_sums(uint32_t *__restrict__ partial, 
     return over;
 }
 
+constexpr int kScanPer = 8;                       // tiles per thread in one round of the tile scan
+constexpr int kScanWaves = kScanThreads / kWave;  // waves of the scan's workgroup
+
+// LDS of the tile scan: per slice, the waves' totals; the waves' 64-bit count sums
+struct TileScanLds {
+    uint32_t part[kScanPer][kScanWaves];
+    uint64_t tot[kScanWaves];
+};
+
+// One round of tiles r0 + k * kScanThreads + thread (k < kScanPer: each slice of
+// kScanThreads consecutive tiles is read with coalesced loads, all issued together).
+__device__ __forceinline__ void load_counts(const uint32_t *__restrict__ cnt_g, const uint32_t *__restrict__ cnt_n,
+                                            int tiles, int r0, uint32_t (&g)[kScanPer], uint32_t (&n)[kScanPer]) {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int i = r0 + k * kScanThreads + (int)threadIdx.x;
+        g[k] = i < tiles ? cnt_g[i] : 0u;
+        n[k] = i < tiles ? cnt_n[i] : 0u;
+    }
+}
+
+// Wave-inclusive scans of the round's slices; the waves' slice totals go to LDS.
+__device__ __forceinline__ void round_publish(const uint32_t (&c)[kScanPer], uint32_t (&inc)[kScanPer],
+                                              TileScanLds &L) {
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        inc[k] = wave_incl_scan(c[k]);
+        if (lane_id() == kWave - 1) L.part[k][w] = inc[k];
+    }
+}
+
+// After the barrier that follows round_publish: writes the round's ranges and cursors
+// (starting at carry; all empty if `empty`) and clears its counters; returns the
+// round's total.
+__device__ __forceinline__ uint32_t round_write(const uint32_t (&g)[kScanPer], const uint32_t (&c)[kScanPer],
+                                                const uint32_t (&inc)[kScanPer], const TileScanLds &L,
+                                                uint32_t carry, int r0, int tiles, bool empty,
+                                                uint32_t *__restrict__ ranges, uint32_t *__restrict__ cur_n,
+                                                uint32_t *__restrict__ cnt_g, uint32_t *__restrict__ cnt_n) {
+    const int w = threadIdx.x / kWave;
+    uint32_t running = carry;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        uint32_t row = 0, before = 0;
+#pragma unroll
+        for (int v = 0; v < kScanWaves; ++v) {
+            const uint32_t x = L.part[k][v];
+            row += x;
+            before += v < w ? x : 0u;
+        }
+        const uint32_t start = empty ? 0u : running + before + inc[k] - c[k];
+        const int i = r0 + k * kScanThreads + (int)threadIdx.x;
+        if (i < tiles) {
+            ranges[2 * i] = start;
+            ranges[2 * i + 1] = empty ? 0u : start + c[k];
+            cur_n[i] = start + g[k];
+            cnt_g[i] = 0u;
+            cnt_n[i] = 0u;
+        }
+        running += row;
+    }
+    return running - carry;
+}
+
 // Exclusive scan of the tile counts (grouped + ungrouped) into ranges and the ungrouped
 // cursors (start + grouped count); the counters are left zero for the next frame.
 // Ranges are empty on overflow, and also when the tile counts do not add up to the
 // instance total `expect` (counters that were not zero when the count pass started: a
 // workspace that was not initialised); then misc and *d_status report INVALID_ARG.
+// Up to kScanThreads * kScanPer tiles (1352 x 1014 has 5,440) take one round: one batch
+// of loads, one barrier.  Larger images add the counts up first (the check needs the
+// total before any range is written), then scan round by round.
 __device__ __forceinline__ void scan_tiles(uint32_t *__restrict__ cnt_g, uint32_t *__restrict__ cnt_n,
                                            uint32_t *__restrict__ cur_n, int tiles, uint32_t *__restrict__ ranges,
                                            bool over, uint64_t expect, uint32_t *__restrict__ misc,
-                                           int32_t *__restrict__ d_status, uint32_t *wsum) {
-    const int tid = threadIdx.x;
-    const int per = (tiles + kScanThreads - 1) / kScanThreads;
-    const int i0 = min(tiles, tid * per), i1 = min(tiles, i0 + per);
-    uint64_t s64 = 0;
-    for (int i = i0; i < i1; ++i) s64 += over ? 0u : (uint64_t)cnt_g[i] + cnt_n[i];
-    const uint32_t s = (uint32_t)min(s64, (uint64_t)0xffffffffull);
-    const uint32_t inc = wave_incl_scan(s);
-    if (lane_id() == kWave - 1) wsum[tid / kWave] = inc;
-    __syncthreads();
-    uint32_t base = 0;
-    uint64_t total = 0;
-    for (int i = 0; i < kScanThreads / kWave; ++i) {
-        base += (i < tid / kWave) ? wsum[i] : 0u;
-        total += wsum[i];
+                                           int32_t *__restrict__ d_status, TileScanLds &L) {
+    const int tid = threadIdx.x, w = tid / kWave;
+    constexpr int RS = kScanThreads * kScanPer;
+    uint32_t g[kScanPer], n[kScanPer], c[kScanPer], inc[kScanPer];
+    uint64_t mine = 0;
+    const bool one = tiles <= RS;
+    if (one) {
+        load_counts(cnt_g, cnt_n, tiles, 0, g, n);
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            mine += (uint64_t)g[k] + n[k];
+            c[k] = g[k] + n[k];
+        }
+        round_publish(c, inc, L);
+    } else {
+        for (int r0 = 0; r0 < tiles; r0 += RS) {
+            load_counts(cnt_g, cnt_n, tiles, r0, g, n);
+#pragma unroll
+            for (int k = 0; k < kScanPer; ++k) mine += (uint64_t)g[k] + n[k];
+        }
     }
-    const bool bad = !over && (s64 != s || total != expect);
-    const bool empty = over || __syncthreads_or(bad);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) mine += __shfl_xor(mine, o, kWave);
+    if (lane_id() == 0) L.tot[w] = mine;
+    __syncthreads();
+    uint64_t total = 0;
+#pragma unroll
+    for (int v = 0; v < kScanWaves; ++v) total += L.tot[v];
+    const bool empty = over || total != expect;  // otherwise every prefix fits: total <= capacity < 2^31
     if (tid == 0 && empty && !over) {
         misc[0] = 0u;
         misc[1] = (uint32_t)D4DGS_ERR_INVALID_ARG;
         if (d_status) *d_status = D4DGS_ERR_INVALID_ARG;
     }
-    uint32_t run = empty ? 0u : base + inc - s;
-    for (int i = i0; i < i1; ++i) {
-        const uint32_t g = cnt_g[i], c = empty ? 0u : g + cnt_n[i];
-        ranges[2 * i] = run;
-        ranges[2 * i + 1] = run + c;
-        cur_n[i] = run + g;
-        cnt_g[i] = 0u;
-        cnt_n[i] = 0u;
-        run += c;
+    if (one) {
+        round_write(g, c, inc, L, 0u, 0, tiles, empty, ranges, cur_n, cnt_g, cnt_n);
+        return;
+    }
+    uint32_t carry = 0;
+    for (int r0 = 0; r0 < tiles; r0 += RS) {
+        load_counts(cnt_g, cnt_n, tiles, r0, g, n);
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) c[k] = g[k] + n[k];
+        round_publish(c, inc, L);
+        __syncthreads();
+        carry += round_write(g, c, inc, L, carry, r0, tiles, empty, ranges, cur_n, cnt_g, cnt_n);
+        __syncthreads();  // the next round rewrites L.part
     }
 }
 
@@ -159,11 +242,11 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
                                                            uint32_t *__restrict__ cur_n, int tiles,
                                                            uint32_t *__restrict__ ranges, uint32_t *__restrict__ misc,
                                                            int32_t *__restrict__ d_status) {
-    __shared__ uint32_t wsum[kScanThreads / kWave];
+    __shared__ TileScanLds L;
     const bool over = misc[1] != 0u;
     const uint64_t expect = misc[0];
     __syncthreads();  // every thread has read misc before thread 0 may rewrite it
-    scan_tiles(cnt_g, cnt_n, cur_n, tiles, ranges, over, expect, misc, d_status, wsum);
+    scan_tiles(cnt_g, cnt_n, cur_n, tiles, ranges, over, expect, misc, d_status, L);
 }
 
 // Both scans in one workgroup, after the projection that counted the instances (its
@@ -177,10 +260,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_both(uint32_t *__restrict
                                                            uint32_t *__restrict__ cur_n, int tiles,
                                                            uint32_t *__restrict__ ranges) {
     __shared__ uint64_t wsum64[kScanThreads / kWave];
-    __shared__ uint32_t wsum32[kScanThreads / kWave];
+    __shared__ TileScanLds L;
     uint64_t total;
     const bool over = scan_block_sums(partial, nb, capacity, num_inst, misc, d_status, wsum64, &total);
-    scan_tiles(cnt_g, cnt_n, cur_n, tiles, ranges, over, total, misc, d_status, wsum32);
+    scan_tiles(cnt_g, cnt_n, cur_n, tiles, ranges, over, total, misc, d_status, L);
 }
 
 // Tile order of the per-tile launches (see tile_unit): the tiles of row class x (rows

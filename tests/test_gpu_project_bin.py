@@ -136,6 +136,15 @@ def test_fused_full_size_frame(R):
         assert run_both(fused, sep, cams[j], np.float32(t))["num_inst"] > 0
 
 
+def test_fused_large_image_scans_in_rounds(R):
+    """2704 x 2028 has 21,463 tiles: the tile scan adds the counts up first, then scans
+    in three rounds of 8,192."""
+    sc = inputs.config2_scene(n=30_000)
+    cam, t = inputs.config5_views()[1]
+    ds, fused, sep = renderers(R, sc, cam.width, cam.height)
+    assert run_both(fused, sep, cam, t)["num_inst"] > 0
+
+
 def test_fused_overflow_then_a_frame_that_fits(R):
     from paper_2503_22159_amd import binding as B
 
