@@ -21,7 +21,7 @@
 //                    kRankMax keys are sorted by ranking: the keys are unique, so a key's
 //                    sorted position is the number of smaller keys, counted by each thread
 //                    for its own (up to two) keys while the wavefront streams the bucket
-//                    from LDS, two keys per broadcast read (a bucket of at most 64 keys
+//                    from LDS, two keys per broadcast read (a bucket of at most 128 keys
 //                    takes one wavefront and no barrier).  Larger buckets: stable
 //                    least-significant-digit radix sort over the 64 key bits, 8-bit digits,
 //                    ping-ponging between two global scratch arrays.  Writes
@@ -470,6 +470,44 @@ __device__ __forceinline__ void rank2(const uint64_t *sk, uint32_t s, uint64_t k
     }
 }
 
+// One wavefront sorts a bucket of s <= 64 NQ keys: lane l holds keys l + 64 q (q < NQ),
+// stages them in sk, and ranks them against the whole bucket, two keys per broadcast.
+// Buckets up to kOneWaveMax keys take this path (the other three wavefronts of the
+// workgroup exit at once): fewer resident waves for the same comparisons.  Measured
+// (sweep frames/s): 64 keys 22.7 k, 128 keys 22.9 k, 256 keys 22.6 k.
+constexpr int kOneWaveMax = 128;
+template <int NQ>
+__device__ __forceinline__ void wave_rank_sort(const uint64_t *__restrict__ bucket, uint32_t start, uint32_t s,
+                                               uint64_t *sk, uint32_t tile, uint64_t *__restrict__ keys,
+                                               uint32_t *__restrict__ vals) {
+    const uint32_t ln = lane_id();
+    uint64_t k[NQ];
+    uint32_t r[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const uint32_t i = ln + kWave * q;
+        k[q] = i < s ? bucket[start + i] : ~0ull;
+        r[q] = 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sk[ln + kWave * q] = k[q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(sk);
+    const uint32_t np = (s + 1) >> 1;
+    for (uint32_t j = 0; j < np; ++j) {
+        const ulonglong2 kk = p[j];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) r[q] += (kk.x < k[q]) + (kk.y < k[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const uint32_t i = ln + kWave * q;
+        if (i < s) write_out(k[q], start + r[q], tile, keys, vals);
+    }
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint64_t *__restrict__ bucket,
                                                             uint64_t *__restrict__ alt,
                                                             const uint32_t *__restrict__ ranges, int tiles,
@@ -488,25 +526,24 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint64_t *__re
     const uint32_t s = end - start;
     const uint32_t tid = threadIdx.x;
     if (s == 0) return;
+    if (s <= (uint32_t)kOneWaveMax) {
+        if (tid >= (uint32_t)kWave) return;
+        switch ((s + kWave - 1) / kWave) {
+            case 1: wave_rank_sort<1>(bucket, start, s, sk, (uint32_t)tile, keys, vals); break;
+            default: wave_rank_sort<2>(bucket, start, s, sk, (uint32_t)tile, keys, vals); break;
+        }
+        return;
+    }
     if (s <= (uint32_t)kRankMax) {
-        // the bucket is staged in LDS (coalesced loads) and every key is ranked against it;
-        // a bucket of one wavefront's keys is handled by that wavefront alone, without a
-        // workgroup barrier
+        // the workgroup stages the bucket in LDS (coalesced loads) and every thread ranks
+        // its (up to two) keys against it
         const uint32_t i1 = tid + kSortThreads;
-        const bool one = s <= (uint32_t)kWave;
-        if (one && tid >= (uint32_t)kWave) return;
         const uint64_t k0 = tid < s ? bucket[start + tid] : ~0ull;
         const uint64_t k1 = i1 < s ? bucket[start + i1] : ~0ull;
         sk[tid] = k0;
-        if (!one) {
-            sk[i1] = k1;
-            __syncthreads();
-            if ((tid & ~(uint32_t)(kWave - 1)) >= s) return;  // a wavefront without keys
-        } else {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
+        sk[i1] = k1;
+        __syncthreads();
+        if ((tid & ~(uint32_t)(kWave - 1)) >= s) return;  // a wavefront without keys
         uint32_t r0 = 0, r1 = 0;
         if (s <= (uint32_t)kSortThreads)
             rank2<false>(sk, s, k0, k1, r0, r1);
