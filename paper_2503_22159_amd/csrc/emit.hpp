@@ -46,8 +46,10 @@ __device__ __forceinline__ void rect_of(uint32_t lo, uint32_t hi, uint32_t &x0, 
 
 // Stages this thread's count and rectangle (lo, hi: its record's rectangle bits, read
 // only when cnt > 0) and returns the block's union rectangle, with the grouped cells
-// cleared.  Contains block-wide barriers: every thread of the block calls it.
-__device__ __forceinline__ EmitBox emit_box(EmitLds &L, uint32_t cnt, uint32_t lo, uint32_t hi) {
+// cleared.  block_sum (optional) receives the block's count sum, from the wave prefixes.
+// Contains block-wide barriers: every thread of the block calls it.
+__device__ __forceinline__ EmitBox emit_box(EmitLds &L, uint32_t cnt, uint32_t lo, uint32_t hi,
+                                            uint32_t *block_sum = nullptr) {
     const int tid = threadIdx.x, wv = tid / kWave;
     L.incl[tid] = wave_incl_scan(cnt);
     uint32_t bx0 = 0xffffu, by0 = 0xffffu, bx1 = 0u, by1 = 0u;
@@ -71,6 +73,12 @@ __device__ __forceinline__ EmitBox emit_box(EmitLds &L, uint32_t cnt, uint32_t l
         L.box[3][wv] = by1;
     }
     __syncthreads();
+    if (block_sum && tid == 0) {
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kBlock / kWave; ++i) sum += L.incl[i * kWave + kWave - 1];
+        *block_sum = sum;
+    }
 #pragma unroll
     for (int i = 0; i < kBlock / kWave; ++i) {
         bx0 = min(bx0, L.box[0][i]);
@@ -114,11 +122,12 @@ __device__ __forceinline__ void emit_each(const EmitLds &L, const EmitBox &B, in
 
 // The count pass of one block (block index blk): grouped, per-tile counts in LDS and one
 // reservation per (block, tile) on cnt_g, its offset kept in grp_off[blk][cell];
-// otherwise one increment of cnt_n per instance.  Block-wide barriers.
+// otherwise one increment of cnt_n per instance.  block_sum (optional) receives the
+// block's count sum.  Block-wide barriers.
 __device__ __forceinline__ void emit_count(EmitLds &L, uint32_t cnt, uint32_t lo, uint32_t hi, int TX, int blk,
                                            uint32_t *__restrict__ cnt_g, uint32_t *__restrict__ cnt_n,
-                                           uint32_t *__restrict__ grp_off) {
-    const EmitBox B = emit_box(L, cnt, lo, hi);
+                                           uint32_t *__restrict__ grp_off, uint32_t *block_sum = nullptr) {
+    const EmitBox B = emit_box(L, cnt, lo, hi, block_sum);
     if (B.grouped) {
         emit_each(L, B, TX, [&](int, uint32_t, uint32_t cell) { atomicAdd(&L.cell[cell], 1u); });
         __syncthreads();

@@ -310,10 +310,11 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneK s, CamK c, float t, f
         }
         count[gi] = cnt;
     }
-    block_count_sum(cnt, block_sums);
-    if (BIN) {
+    if (BIN) {  // the count pass also writes the block's count sum
         __shared__ EmitLds L;
-        emit_count(L, cnt, rlo, rhi, bin.TX, blockIdx.x, bin.cnt_g, bin.cnt_n, bin.grp_off);
+        emit_count(L, cnt, rlo, rhi, bin.TX, blockIdx.x, bin.cnt_g, bin.cnt_n, bin.grp_off, &block_sums[blockIdx.x]);
+    } else {
+        block_count_sum(cnt, block_sums);
     }
 }
 
