@@ -377,10 +377,19 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const float4 *__restrict__ r
         s_dbits[tid] = __float_as_uint(r2.y);
     }
     const EmitBox B = emit_box(L, cnt, lo, hi);
+    if (B.grouped) {
+        // each cell's first free position, the tile's start + the block's reservation,
+        // loaded for the whole union rectangle at once (a cell without instances reads a
+        // reservation the count pass did not write, and never uses it); an LDS atomic on
+        // it then hands out the positions
+        for (uint32_t c = tid; c < B.uw * B.uh; c += kBlock) {
+            const uint32_t tile = (B.by0 + c / B.uw) * (uint32_t)TX + (B.bx0 + c % B.uw);
+            L.cell[c] = ranges[2 * tile] + grp_off[(size_t)blk * kCells + c];
+        }
+        __syncthreads();
+    }
     emit_each(L, B, TX, [&](int o, uint32_t tile, uint32_t cell) {
-        const uint32_t pos = B.grouped ? ranges[2 * tile] + grp_off[(size_t)blk * kCells + cell] +
-                                             atomicAdd(&L.cell[cell], 1u)
-                                       : atomicAdd(&cur_n[tile], 1u);
+        const uint32_t pos = B.grouped ? atomicAdd(&L.cell[cell], 1u) : atomicAdd(&cur_n[tile], 1u);
         if (pos < total)  // always, when the counters started at zero; a guard for the bucket otherwise
             bucket[pos] = ((uint64_t)s_dbits[o] << 32) | (uint32_t)(blk * kBlock + o);
     });
