@@ -157,6 +157,7 @@ struct d4dgs_server {
     bool stop = false;
     std::thread th;
     d4dgs_serve_stats stats{};
+    int64_t last_activity_ns = 0;  // last launch or retirement (for the polling policy)
 
     void run();
     bool retire_one(Batch &b);
@@ -285,7 +286,10 @@ void d4dgs_server::run() {
                 ++i;
             }
         }
-        if (retired) cv_done.notify_all();
+        if (retired) {
+            last_activity_ns = now_ns();
+            cv_done.notify_all();
+        }
         // 2. admit waiting requests, oldest first
         Batch b;
         while (!pending.empty() && inflight_reqs < cfg.max_inflight && (int)b.reqs.size() < cfg.max_batch &&
@@ -313,13 +317,22 @@ void d4dgs_server::run() {
         if (!b.reqs.empty()) {
             launch(b);
             if (!b.reqs.empty()) inflight.push_back(b);
+            last_activity_ns = now_ns();
             continue;
         }
         if (stop && pending.empty() && inflight.empty()) break;
         if (!inflight.empty()) {
-            // poll the GPU: short sleeps keep completion latency low
+            // poll the GPU.  Within kSpinNs of the last launch or retirement (a frame takes
+            // ~0.1-0.5 ms) the thread spins, yielding the CPU between queries, so a
+            // completion is seen within microseconds (a 20 us sleep takes 60-80 us on
+            // Linux: timer slack); after that, short sleeps.
+            constexpr int64_t kSpinNs = 2000000;
+            const bool spin = now_ns() - last_activity_ns < kSpinNs;
             lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            if (spin)
+                std::this_thread::yield();
+            else
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
             lk.lock();
         } else {
             cv_work.wait_for(lk, std::chrono::milliseconds(5));
