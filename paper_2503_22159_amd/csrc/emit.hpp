@@ -4,14 +4,15 @@
 //
 // Device-scope atomics are expensive on this part, so the count pass aggregates them:
 // when the block's splats together cover at most kCells tiles (a spatially coherent
-// block: the scene is stored in 3D Morton order), its instances are counted per tile in
-// LDS and one atomic per (block, tile) on the tile's grouped counter reserves the
-// group's range, kept in grp_off[block][cell]; otherwise every instance adds one to the
-// tile's ungrouped counter.  After the tile scan a tile's list is laid out as
-// [grouped instances | ungrouped instances]; the scatter pass recomputes the same
-// enumeration and places a grouped instance at start + grp_off + a rank from an LDS
-// counter, an ungrouped one at an atomic cursor that starts after the grouped ones (any
-// unique position will do: the per-tile sort fixes the final order).
+// block, as when the scene is stored along a space-filling curve -- the synthetic scenes
+// are in 3D Morton order), its instances are counted per tile in LDS and one atomic per
+// (block, tile) on the tile's grouped counter reserves the group's range, kept in
+// grp_off[block][cell]; otherwise every instance adds one to the tile's ungrouped
+// counter.  After the tile scan a tile's list is laid out as [grouped instances |
+// ungrouped instances]; the scatter pass recomputes the same enumeration and places a
+// grouped instance at start + grp_off + its rank inside the group (an LDS atomic), an
+// ungrouped one at an atomic cursor that starts after the grouped ones (any unique
+// position will do: the per-tile sort fixes the final order).
 #pragma once
 
 #include "internal.hpp"
