@@ -60,13 +60,10 @@ __device__ __forceinline__ EmitBox emit_box(EmitLds &L, uint32_t cnt, uint32_t l
         L.y0[tid] = by0;
         L.w[tid] = bx1 - bx0;
     }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        bx0 = min(bx0, (uint32_t)__shfl_xor((int)bx0, o, kWave));
-        by0 = min(by0, (uint32_t)__shfl_xor((int)by0, o, kWave));
-        bx1 = max(bx1, (uint32_t)__shfl_xor((int)bx1, o, kWave));
-        by1 = max(by1, (uint32_t)__shfl_xor((int)by1, o, kWave));
-    }
+    bx0 = wave_min_u32_uniform(bx0);
+    by0 = wave_min_u32_uniform(by0);
+    bx1 = wave_max_u32_uniform(bx1);
+    by1 = wave_max_u32_uniform(by1);
     if (lane_id() == 0) {
         L.box[0][wv] = bx0;
         L.box[1][wv] = by0;

@@ -45,14 +45,46 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return (uint64_t(1) << lane_id()) - 1;  // lane 0 -> 0
 }
 
-// inclusive prefix sum over the wave (Hillis-Steele with cross-lane shuffles)
+// DPP move of a 32-bit value (row_mask selects the 16-lane rows that are written; the
+// others get 0).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Inclusive prefix sum over the wave with DPP (no LDS): Hillis-Steele inside each row of
+// 16 lanes (shifts by 1, 2, 4, 8; lanes shifted in from outside the row add 0), then
+// row 0's total is added to row 1 and row 2's to row 3 (row_bcast:15), then the total of
+// rows 0-1 to rows 2-3 (row_bcast:31).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        uint32_t u = __shfl_up(v, o, kWave);
-        if (lane_id() >= o) v += u;
-    }
+    v += dpp_u32<0x111>(v);       // row_shr:1
+    v += dpp_u32<0x112>(v);       // row_shr:2
+    v += dpp_u32<0x114>(v);       // row_shr:4
+    v += dpp_u32<0x118>(v);       // row_shr:8
+    v += dpp_u32<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_u32<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     return v;
+}
+
+// Wave minimum / maximum, uniform: DPP inside each row (partners l ^ 1, l ^ 2, rotations
+// by 4 and 8), then the four rows' values through scalar registers.
+__device__ __forceinline__ uint32_t wave_min_u32_uniform(uint32_t v) {
+    v = min(v, dpp_u32<0xB1>(v));
+    v = min(v, dpp_u32<0x4E>(v));
+    v = min(v, dpp_u32<0x124>(v));
+    v = min(v, dpp_u32<0x128>(v));
+    const uint32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    const uint32_t c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return min(min(a, b), min(c, d));
+}
+__device__ __forceinline__ uint32_t wave_max_u32_uniform(uint32_t v) {
+    v = max(v, dpp_u32<0xB1>(v));
+    v = max(v, dpp_u32<0x4E>(v));
+    v = max(v, dpp_u32<0x124>(v));
+    v = max(v, dpp_u32<0x128>(v));
+    const uint32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    const uint32_t c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return max(max(a, b), max(c, d));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
