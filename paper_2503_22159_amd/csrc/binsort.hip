@@ -65,12 +65,7 @@ __device__ __forceinline__ bool scan_block_sums(uint32_t *__restrict__ partial, 
     const int b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
     uint64_t s = 0;
     for (int i = b0; i < b1; ++i) s += partial[i];
-    uint64_t inc = s;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint64_t u = __shfl_up(inc, o, kWave);
-        if (lane_id() >= o) inc += u;
-    }
+    const uint64_t inc = wave_incl_scan64(s);
     if (lane_id() == kWave - 1) wsum[tid / kWave] = inc;
     __syncthreads();
     uint64_t base = 0, total = 0;
@@ -192,8 +187,7 @@ __device__ __forceinline__ void scan_tiles(uint32_t *__restrict__ cnt_g, uint32_
             for (int k = 0; k < kScanPer; ++k) mine += (uint64_t)g[k] + n[k];
         }
     }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) mine += __shfl_xor(mine, o, kWave);
+    mine = wave_sum_u64_uniform(mine);
     if (lane_id() == 0) L.tot[w] = mine;
     __syncthreads();
     uint64_t total = 0;

@@ -66,6 +66,46 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+// The same on 64-bit values (both halves moved by DPP).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    const uint32_t lo = dpp_u32<CTRL, ROW_MASK>((uint32_t)v), hi = dpp_u32<CTRL, ROW_MASK>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
+    v += dpp_u64<0x111>(v);
+    v += dpp_u64<0x112>(v);
+    v += dpp_u64<0x114>(v);
+    v += dpp_u64<0x118>(v);
+    v += dpp_u64<0x142, 0xa>(v);
+    v += dpp_u64<0x143, 0xc>(v);
+    return v;
+}
+
+// Wave sums, uniform: DPP inside each row (partners l ^ 1, l ^ 2, rotations by 4 and 8),
+// then the four rows' values through scalar registers.
+__device__ __forceinline__ uint32_t wave_sum_u32_uniform(uint32_t v) {
+    v += dpp_u32<0xB1>(v);
+    v += dpp_u32<0x4E>(v);
+    v += dpp_u32<0x124>(v);
+    v += dpp_u32<0x128>(v);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+           __builtin_amdgcn_readlane(v, 48);
+}
+__device__ __forceinline__ uint64_t wave_sum_u64_uniform(uint64_t v) {
+    v += dpp_u64<0xB1>(v);
+    v += dpp_u64<0x4E>(v);
+    v += dpp_u64<0x124>(v);
+    v += dpp_u64<0x128>(v);
+    uint64_t t = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        t += ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), 16 * r) << 32) |
+             __builtin_amdgcn_readlane((uint32_t)v, 16 * r);
+    return t;
+}
+
 // Wave minimum / maximum, uniform: DPP inside each row (partners l ^ 1, l ^ 2, rotations
 // by 4 and 8), then the four rows' values through scalar registers.
 __device__ __forceinline__ uint32_t wave_min_u32_uniform(uint32_t v) {

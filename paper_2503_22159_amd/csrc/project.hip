@@ -214,9 +214,7 @@ __device__ __forceinline__ uint32_t time_stage(const CamRec &cr, float o_, float
 // Block-wide sum of the counts (for the two-level scan in the binning stage).
 __device__ __forceinline__ void block_count_sum(uint32_t cnt, uint32_t *block_sums) {
     __shared__ uint32_t part[kBlock / kWave];
-    uint32_t v = cnt;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, kWave);
+    const uint32_t v = wave_sum_u32_uniform(cnt);
     if (lane_id() == 0) part[threadIdx.x / kWave] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
