@@ -250,9 +250,9 @@ def view_steps(inputs, render):
     out = {}
     for name in ("c3_8x800x800_100k", "c5_4x2704x2028_2M"):
         if name.startswith("c3"):
-            sc, views, _ = inputs.config3()
+            sc, views, _ = inputs.fit_case()
         else:
-            sc, views = inputs.config5_scene(), inputs.config5_views()
+            sc, views = inputs.large_scene(), inputs.large_views()
         ds = render.DeviceScene.from_inputs(sc)
         scene_bytes = sum(x.numel() * x.element_size() for x in ds.t.values())
         del sc
@@ -368,9 +368,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
-    scene = inputs.config2_scene()
+    scene = inputs.clustered_scene()
     ds = render.DeviceScene.from_inputs(scene)
-    cams = inputs.config2_cameras()
+    cams = inputs.arc_cameras()
     times = [np.float32(k / (args.frames - 1)) for k in range(args.frames)]
     W, H = cams[0].width, cams[0].height
 

@@ -187,8 +187,8 @@ def perturb_raw(scene: Scene, seed, std=0.01) -> Scene:
     return scene_from_raw(raw, scene.sh_degree)
 
 
-# ----------------------------------------------------------------------------- configs
-def config1():
+# ----------------------------------------------------------------------------- workloads
+def small_case():
     """2,000 Gaussians, 128x128, SH0, t = 0.5 (correctness case)."""
     sc = make_scene(1, 2000, 0, box=(-2.0, 2.0), log_scale=(-3.0, 0.3), dc=(0.5, 0.2),
                     t_scale_range=(0.05, 0.5), vel_std=0.2)
@@ -196,7 +196,7 @@ def config1():
     return sc, cam, np.float32(0.5)
 
 
-def config2_scene(n=300_000, seed=2, sh_degree=3):
+def clustered_scene(n=300_000, seed=2, sh_degree=3):
     """Plenoptic-like: 32-cluster mixture in [-5,5]^3, SH3."""
     return make_scene(seed, n, sh_degree, clusters=32, cluster_box=(-5.0, 5.0), cluster_std=0.8,
                       log_scale=(-4.5, 0.6), dc=(0.5, 0.2), rest_std=0.05,
@@ -208,11 +208,11 @@ def arc_camera(j, n_cams=20, radius=10.0, width=1352, height=1014):
     return look_at((radius * math.sin(th), 0.0, -radius * math.cos(th)), width=width, height=height)
 
 
-def config2_cameras(width=1352, height=1014):
+def arc_cameras(width=1352, height=1014):
     return [arc_camera(j, 20, 10.0, width, height) for j in range(20)]
 
 
-def config2_times(k=300):
+def sweep_times(k=300):
     return [np.float32(i / (k - 1)) for i in range(k)]
 
 
@@ -222,10 +222,10 @@ def sphere_camera(rng, radius, width, height):
     return look_at(radius * d, width=width, height=height)
 
 
-def config3(n=100_000):
-    """Differentiation case: C2 distributions with SH1, 8 random (camera, t) views
+def fit_case(n=100_000):
+    """Differentiation case: clustered-scene distributions with SH1, 8 random (camera, t) views
     at 800x800, target = the same scene with N(0, 0.01) noise on raw parameters."""
-    sc = config2_scene(n=n, seed=3, sh_degree=1)
+    sc = clustered_scene(n=n, seed=3, sh_degree=1)
     rng = np.random.default_rng(1003)
     views = []
     for _ in range(8):
@@ -239,11 +239,11 @@ RES_CHOICES = ((640, 480), (1352, 1014), (1920, 1080))
 RES_PROBS = (0.5, 0.3, 0.2)
 
 
-def config4_scene(n=500_000):
-    return config2_scene(n=n, seed=4, sh_degree=3)
+def serving_scene(n=500_000):
+    return clustered_scene(n=n, seed=4, sh_degree=3)
 
 
-def config4_requests(rate=200.0, duration=60.0, seed=1004):
+def serving_requests(rate=200.0, duration=60.0, seed=1004):
     """Poisson arrivals; each request: camera on the radius-10 sphere, t ~ U[0,1],
     resolution from {640x480: 0.5, 1352x1014: 0.3, 1920x1080: 0.2}."""
     rng = np.random.default_rng(seed)
@@ -259,13 +259,13 @@ def config4_requests(rate=200.0, duration=60.0, seed=1004):
     return reqs
 
 
-def config5_scene(n=2_000_000):
+def large_scene(n=2_000_000):
     return make_scene(5, n, 3, clusters=128, cluster_box=(-10.0, 10.0), cluster_std=0.8,
                       log_scale=(-5.0, 0.7), dc=(0.5, 0.2), rest_std=0.05,
                       t_scale_range=(0.01, 0.5), vel_std=0.15)
 
 
-def config5_views(width=2704, height=2028):
+def large_views(width=2704, height=2028):
     out = []
     for th, t in zip((-45.0, -15.0, 15.0, 45.0), (0.125, 0.375, 0.625, 0.875)):
         r = math.radians(th)

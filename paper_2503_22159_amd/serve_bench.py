@@ -1,6 +1,6 @@
 """Serving measurement: a Poisson stream of render requests against one resident scene.
 
-The request stream follows the serving workload: 500k Gaussians (config-2 distributions,
+The request stream follows the serving workload: 500k Gaussians (the clustered scene's distributions,
 SH3) resident on the GPU; arrivals at 200 requests/s; each request a camera on the
 radius-10 sphere, t ~ U[0, 1], resolution 640x480 / 1352x1014 / 1920x1080 with
 probabilities 0.5 / 0.3 / 0.2; at most 64 requests on the GPU, admitted by an 8 GiB
@@ -77,9 +77,9 @@ def run(seconds=10.0, rate=200.0, n=500_000, burst=64, seed=1004):
     from . import inputs, render
     from .serve import Server
 
-    scene = inputs.config4_scene(n=n)
+    scene = inputs.serving_scene(n=n)
     ds = render.DeviceScene.from_inputs(scene)
-    reqs = inputs.config4_requests(rate=rate, duration=seconds, seed=seed)
+    reqs = inputs.serving_requests(rate=rate, duration=seconds, seed=seed)
     ring = 128
     outs = [{(w, h): torch.empty((3, h, w), dtype=torch.float32, device="cuda") for (w, h) in inputs.RES_CHOICES}
             for _ in range(ring)]

@@ -3,7 +3,7 @@
 The upstream gradient is a seeded random image (a fixed linear functional of the
 render).  Pixels the oracle flags as holding a near-threshold evaluation get zero
 upstream gradient on both sides, so both differentiate the same discrete decisions.
-Bar (the benchmark spec): 1e-3 relative -- per parameter group against the group's largest
+Tolerance: 1e-3 relative -- per parameter group against the group's largest
 magnitude, and per element for elements above 1e-2 of it."""
 import numpy as np
 import pytest
@@ -68,7 +68,7 @@ def check_params(gpu, orc):
 def test_instance_gradients_match_oracle_blend_adjoint(R):
     """Stage isolation of the blend adjoint: per-Gaussian sums of the per-instance
     gradient slots equal the oracle's analytic blend adjoint on the same record."""
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     ds, st, g, go, gs_o, nmask = run_both(R, sc, cam, t, seed=11)
     n = sc.n
     rec = decode_record(st, n)
@@ -84,17 +84,17 @@ def test_instance_gradients_match_oracle_blend_adjoint(R):
     compare_group("rgb", sums[:, 6:9].T, gs_o["rgb"])
 
 
-def test_parameter_gradients_config1(R):
-    sc, cam, t = inputs.config1()
+def test_parameter_gradients_small_case(R):
+    sc, cam, t = inputs.small_case()
     ds, st, g, go, gs_o, nmask = run_both(R, sc, cam, t, seed=12, bg=(0.1, 0.3, 0.2))
     errs = check_params(g, go)
-    print("config1 grad rel err", errs, "masked px", nmask)
+    print("small_case grad rel err", errs, "masked px", nmask)
 
 
 @pytest.mark.parametrize("view", [0, 3, 6])
 def test_parameter_gradients_c3_subset(R, view):
     """Config-3 distributions (SH1) at a reduced size: 20k Gaussians, 256x256 views."""
-    sc, views, _ = inputs.config3(n=20_000)
+    sc, views, _ = inputs.fit_case(n=20_000)
     cam0, t = views[view]
     cam = inputs.look_at(cam0.campos, width=256, height=256)
     ds, st, g, go, gs_o, nmask = run_both(R, sc, cam, t, seed=100 + view)
@@ -105,7 +105,7 @@ def test_parameter_gradients_c3_subset(R, view):
 def test_parameter_gradients_opaque_splats(R):
     """Every other Gaussian nearly opaque (alpha at the 0.99 clamp, the general per-splat
     path of forward and backward) next to plain ones."""
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     sc = sc.subset(np.arange(sc.n))
     sc.opacity[::2] = np.float32(0.9995)
     sc.t_scale[::2] = np.float32(0.5)
@@ -120,7 +120,7 @@ def test_split_statistics_accumulate_per_view(R):
     per-view parameter gradients)."""
     import torch
 
-    sc, cam, _ = inputs.config1()
+    sc, cam, _ = inputs.small_case()
     views = [(cam, np.float32(0.4)), (inputs.look_at((1.5, 0.5, -5.5), width=128, height=128), np.float32(0.65))]
     ds = R.DeviceScene.from_inputs(sc)
     grads = R.grads_like(ds, split_stats=True)
@@ -147,7 +147,7 @@ def test_split_statistics_accumulate_per_view(R):
 def test_backward_is_deterministic(R):
     import torch
 
-    sc = inputs.config2_scene(n=20_000)
+    sc = inputs.clustered_scene(n=20_000)
     cam = inputs.arc_camera(4, width=200, height=150)
     ds = R.DeviceScene.from_inputs(sc)
     img, st = R.render_forward(ds, cam, np.float32(0.6))
@@ -162,7 +162,7 @@ def test_backward_is_deterministic(R):
 def test_autograd_function_matches_direct_call(R):
     import torch
 
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     params = [torch.from_numpy(np.ascontiguousarray(getattr(sc, k))).cuda().requires_grad_(True) for k in GROUPS]
     target = torch.rand(3, cam.height, cam.width, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
     img = R.render(*params, cam=cam, t=t, sh_degree=sc.sh_degree)
@@ -182,7 +182,7 @@ def test_gradients_against_gpu_finite_differences(R):
     with the largest gradients: agreement within the FP32 noise of the difference."""
     import torch
 
-    sc = inputs.config2_scene(n=3000, sh_degree=1)
+    sc = inputs.clustered_scene(n=3000, sh_degree=1)
     cam = inputs.arc_camera(9, width=96, height=96)
     t = np.float32(0.5)
     ds = R.DeviceScene.from_inputs(sc)
@@ -214,7 +214,7 @@ def test_backward_of_empty_and_all_culled_frames(R):
     temporally culled, runs and adds exact zeros (the image is the background alone)."""
     import torch
 
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     dL = torch.from_numpy(inputs.upstream_grad(31, cam.width, cam.height)).cuda()
     empty = sc.subset(np.arange(0))
     ds = R.DeviceScene.from_inputs(empty)

@@ -1,4 +1,4 @@
-"""The differentiation case at full size: 100k Gaussians (C2 distributions, SH1), 8 views
+"""The differentiation case at full size: 100k Gaussians (clustered-scene distributions, SH1), 8 views
 at 800x800 of random (camera, t), and the L2 loss against a target: the same scene with
 N(0, 0.01) noise on every raw parameter, rendered by the oracle.
 
@@ -30,10 +30,10 @@ def R():
 
 
 @pytest.mark.timeout(400)
-def test_config3_l2_loss_gradients(R):
+def test_fit_case_l2_loss_gradients(R):
     import torch
 
-    sc, views, target_scene = inputs.config3()
+    sc, views, target_scene = inputs.fit_case()
     ds = R.DeviceScene.from_inputs(sc)
     grads = R.grads_like(ds)
     gsum = None
@@ -50,9 +50,9 @@ def test_config3_l2_loss_gradients(R):
         R.render_backward(ds, cam, t, (0.0, 0.0, 0.0), st, torch.from_numpy(dL.astype(np.float32)).cuda(), grads)
         gp, _, _ = oracle.render_grad(sc, cam, t, dL)
         gsum = gp if gsum is None else {k: gsum[k] + gp[k] for k in gsum}
-        print("config3 view", i, "instances", bins["I"], stats)
+        print("fit_case view", i, "instances", bins["I"], stats)
     torch.cuda.synchronize()
     gg = {k: grads[k].cpu().numpy().astype(np.float64) for k in GROUPS}
     errs = {k: compare_group(k, gg[k], gsum[k]) for k in GROUPS}
-    print("config3 loss", loss, "grad rel err", errs)
+    print("fit_case loss", loss, "grad rel err", errs)
     assert loss > 0.0

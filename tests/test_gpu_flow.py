@@ -34,12 +34,12 @@ def _flow_frame(R, sc, cam, t, bg=(0.0, 0.0, 0.0)):
     return ds, img, flow, st
 
 
-@pytest.mark.parametrize("case", ["config1", "c2_subset"])
+@pytest.mark.parametrize("case", ["small_case", "clustered_subset"])
 def test_flow_render_matches_oracle(R, case):
-    if case == "config1":
-        sc, cam, t = inputs.config1()
+    if case == "small_case":
+        sc, cam, t = inputs.small_case()
     else:
-        sc = inputs.config2_scene(n=40_000)
+        sc = inputs.clustered_scene(n=40_000)
         cam, t = inputs.arc_camera(5, width=337, height=253), np.float32(0.6)
     ds, img, flow, st = _flow_frame(R, sc, cam, t, bg=(0.1, 0.2, 0.3))
     proj, bins, res = oracle.render(sc, cam, t, (0.1, 0.2, 0.3), flow=True)
@@ -56,7 +56,7 @@ def test_flow_render_matches_oracle(R, case):
 def test_flow_loss_matches_oracle(R):
     import torch
 
-    sc = inputs.config2_scene(n=40_000)
+    sc = inputs.clustered_scene(n=40_000)
     cam, t = inputs.arc_camera(12, width=301, height=199), np.float32(0.4)
     ds, img, flow, st = _flow_frame(R, sc, cam, t)
     for lam, eps in ((0.1, 1e-6), (2.0, 1e-2)):
@@ -102,7 +102,7 @@ def test_flow_backward_matches_oracle(R):
     oracle's (blend adjoint with flow channels + complex-step projection adjoint)."""
     import torch
 
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     ds, img, flow, st = _flow_frame(R, sc, cam, t)
     proj, bins, res = oracle.render(sc, cam, t, flow=True)
     mask = res["flags"] > 0
@@ -131,7 +131,7 @@ def test_autograd_flow_loss_chain(R):
     """render_with_flow -> flow_gradient_loss -> backward equals the direct calls."""
     import torch
 
-    sc = inputs.config3(n=10_000)[0]
+    sc = inputs.fit_case(n=10_000)[0]
     cam = inputs.look_at((0.0, 2.0, -9.0), width=160, height=120)
     t = np.float32(0.3)
     params = {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k))).cuda().requires_grad_(True)

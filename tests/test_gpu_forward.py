@@ -47,21 +47,21 @@ def check_frame(R, scene, cam, t, bg=(0.0, 0.0, 0.0)):
     return stats
 
 
-def test_config1_end_to_end(R):
-    sc, cam, t = inputs.config1()
+def test_small_case_end_to_end(R):
+    sc, cam, t = inputs.small_case()
     stats = check_frame(R, sc, cam, t)
-    print("config1", stats)
+    print("small_case", stats)
 
 
 @pytest.mark.parametrize("t", [0.0, 0.37, 1.0])
-def test_config1_times_and_background(R, t):
-    sc, cam, _ = inputs.config1()
+def test_small_case_times_and_background(R, t):
+    sc, cam, _ = inputs.small_case()
     check_frame(R, sc, cam, np.float32(t), bg=(0.2, 0.5, 0.9))
 
 
 @pytest.mark.parametrize("wh", [(1, 1), (17, 33), (100, 75), (257, 129)])
 def test_ragged_sizes(R, wh):
-    sc, _, t = inputs.config1()
+    sc, _, t = inputs.small_case()
     cam = inputs.look_at((0.0, 0.0, -6.0), width=wh[0], height=wh[1])
     check_frame(R, sc, cam, t, bg=(0.1, 0.1, 0.1))
 
@@ -69,7 +69,7 @@ def test_ragged_sizes(R, wh):
 def test_c2_scene_several_tiles_subset(R):
     """Config-2 distributions (SH3), 40k Gaussians, a 337x253 view: many tiles, ragged
     tail, oracle in seconds."""
-    sc = inputs.config2_scene(n=40_000)
+    sc = inputs.clustered_scene(n=40_000)
     cam = inputs.arc_camera(7, width=337, height=253)
     for t in (np.float32(0.0), np.float32(0.5)):
         check_frame(R, sc, cam, t)
@@ -77,8 +77,8 @@ def test_c2_scene_several_tiles_subset(R):
 
 def test_c2_full_size_frame(R):
     """300k Gaussians at 1352x1014 (the benchmark's frame), camera 10 of the arc, t = 0.5."""
-    sc = inputs.config2_scene()
-    cam = inputs.config2_cameras()[10]
+    sc = inputs.clustered_scene()
+    cam = inputs.arc_cameras()[10]
     stats = check_frame(R, sc, cam, np.float32(0.5))
     print("c2 full", stats)
 
@@ -101,7 +101,7 @@ def test_opaque_splats_take_the_clamp_path(R):
     """Every other Gaussian nearly opaque: their alpha reaches the 0.99 clamp, so they take
     the blend's general per-splat path (positive-exponent skip and clamp evaluated) and
     share batches with plain splats."""
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     sc = sc.subset(np.arange(sc.n))
     sc.opacity[::2] = np.float32(0.9995)
     sc.t_scale[::2] = np.float32(0.5)
@@ -109,7 +109,7 @@ def test_opaque_splats_take_the_clamp_path(R):
 
 
 def test_empty_and_all_culled(R):
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     empty = sc.subset(np.arange(0))
     ds, img, st = gpu_frame(R, empty, cam, t, bg=(0.3, 0.2, 0.1))
     assert np.array_equal(img, np.broadcast_to(np.float32([0.3, 0.2, 0.1])[:, None, None], img.shape))
@@ -126,7 +126,7 @@ def test_capacity_overflow_is_reported_and_retried(R):
 
     from paper_2503_22159_amd import binding as B
 
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     orc = oracle.bin(oracle.project(sc, cam, t), cam)
     # async path: status word set, no out-of-bounds writes
     ds = R.DeviceScene.from_inputs(sc)
@@ -153,7 +153,7 @@ def test_capacity_overflow_is_reported_and_retried(R):
 def test_deterministic_and_cache_equivalent(R):
     import torch
 
-    sc = inputs.config2_scene(n=30_000)
+    sc = inputs.clustered_scene(n=30_000)
     cam = inputs.arc_camera(3, width=320, height=240)
     ds = R.DeviceScene.from_inputs(sc)
     cache = R.CamCache(sc.n)
@@ -181,7 +181,7 @@ def test_invalid_arguments_rejected(R):
 
     from paper_2503_22159_amd import binding as B
 
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     ds = R.DeviceScene.from_inputs(sc)
     st = R.FrameState(sc.n, cam.width, cam.height, 10000)
     bad = B.camera_struct(cam)
@@ -206,7 +206,7 @@ def test_timed_blend_matches_and_times_the_kernel(R):
 
     from paper_2503_22159_amd import binding as B
 
-    sc = inputs.config2_scene(n=30_000)
+    sc = inputs.clustered_scene(n=30_000)
     cam = inputs.arc_camera(5, width=337, height=253)
     ds = R.DeviceScene.from_inputs(sc)
     rend = R.Renderer(ds, cam.width, cam.height, keep_state=True)
@@ -238,7 +238,7 @@ def test_tile_order_is_longest_first_and_changes_nothing(R):
     those of the row-order launch."""
     import torch
 
-    sc = inputs.config2_scene(n=40_000)
+    sc = inputs.clustered_scene(n=40_000)
     cam = inputs.arc_camera(7, width=337, height=253)
     t = np.float32(0.5)
     ds = R.DeviceScene.from_inputs(sc)

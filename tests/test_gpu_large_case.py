@@ -36,7 +36,7 @@ def R():
 
 @pytest.fixture(scope="module")
 def scene():
-    return inputs.config5_scene()
+    return inputs.large_scene()
 
 
 def sampled_tiles(cam, seed):
@@ -61,10 +61,10 @@ def masked_bins(bins, keep):
 
 
 @pytest.mark.timeout(400)
-def test_config5_batch_forward_backward(R, scene):
+def test_large_case_batch_forward_backward(R, scene):
     import torch
 
-    views = inputs.config5_views()
+    views = inputs.large_views()
     ds = R.DeviceScene.from_inputs(scene)
     torch.cuda.synchronize()
     base = torch.cuda.memory_allocated()
@@ -96,7 +96,7 @@ def test_config5_batch_forward_backward(R, scene):
         R.render_backward(ds, cam, t, (0.0, 0.0, 0.0), st, torch.from_numpy(orc[i][4]).cuda(), grads)
     torch.cuda.synchronize()
     peak = torch.cuda.max_memory_allocated() - base
-    print(f"config5 step: scene {base / 2**30:.2f} GiB resident, peak step memory {peak / 2**30:.2f} GiB")
+    print(f"large_case step: scene {base / 2**30:.2f} GiB resident, peak step memory {peak / 2**30:.2f} GiB")
 
     gsum = None
     for i, (cam, t) in enumerate(views):
@@ -115,7 +115,7 @@ def test_config5_batch_forward_backward(R, scene):
         ri = {"img": np.where(pix[None], res["img"], gi), "flags": np.where(pix, res["flags"], 0),
               "final_T": np.where(pix, res["final_T"], gT), "n_contrib": np.where(pix, res["n_contrib"], gN)}
         stats = compare_images(gi, gT, gN, ri)
-        print("config5 view", i, "instances", gb["I"], "sampled px", int(pix.sum()), stats)
+        print("large_case view", i, "instances", gb["I"], "sampled px", int(pix.sum()), stats)
         gs = oracle.blend_bwd(proj, mb, cam, dL.astype(np.float64))
         touched = (np.abs(gs["m"]).sum(0) + np.abs(gs["conic"]).sum(0) + np.abs(gs["amax"]) +
                    np.abs(gs["rgb"]).sum(0)) > 0
@@ -123,4 +123,4 @@ def test_config5_batch_forward_backward(R, scene):
         gsum = gpar if gsum is None else {k: gsum[k] + gpar[k] for k in gsum}
     gg = {k: grads[k].cpu().numpy().astype(np.float64) for k in GROUPS}
     errs = {k: compare_group(k, gg[k], gsum[k]) for k in GROUPS}
-    print("config5 grad rel err", errs)
+    print("large_case grad rel err", errs)

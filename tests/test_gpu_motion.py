@@ -26,14 +26,14 @@ def R():
 
 
 @pytest.mark.parametrize("mode", MODES)
-@pytest.mark.parametrize("case", ["config1", "c2_subset"])
+@pytest.mark.parametrize("case", ["small_case", "clustered_subset"])
 def test_forward_per_model(R, mode, case):
     import torch
 
-    if case == "config1":
-        sc, cam, t = inputs.config1()
+    if case == "small_case":
+        sc, cam, t = inputs.small_case()
     else:
-        sc = inputs.config2_scene(n=40_000)
+        sc = inputs.clustered_scene(n=40_000)
         cam, t = inputs.arc_camera(9, width=337, height=253), np.float32(0.15)
     ds = R.DeviceScene.from_inputs(sc)
     img, st = R.render_forward(ds, cam, t, (0.1, 0.1, 0.1), motion=mode)
@@ -51,7 +51,7 @@ def test_forward_per_model(R, mode, case):
 def test_gradients_per_model(R, mode):
     import torch
 
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     ds = R.DeviceScene.from_inputs(sc)
     img, st = R.render_forward(ds, cam, t, motion=mode)
     with oracle.motion(mode):
@@ -70,7 +70,7 @@ def test_flow_under_exact_projection(R):
     image + flow upstream terms against the oracle."""
     import torch
 
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     ds = R.DeviceScene.from_inputs(sc)
     img, flow, st = R.render_forward_flow(ds, cam, t, motion=1)
     torch.cuda.synchronize()

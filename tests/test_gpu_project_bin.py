@@ -93,8 +93,8 @@ def run_both(fused, sep, cam, t):
 
 
 @pytest.mark.parametrize("cache", [True, False])
-def test_fused_equals_separate_c2_subset(R, cache):
-    sc = inputs.config2_scene(n=30_000)
+def test_fused_equals_separate_clustered_subset(R, cache):
+    sc = inputs.clustered_scene(n=30_000)
     cams = [inputs.arc_camera(j, width=320, height=240) for j in (3, 7)]
     ds, fused, sep = renderers(R, sc, 320, 240, cache=cache)
     # camera-cache miss, hits at other times, another camera (miss), back (miss)
@@ -106,7 +106,7 @@ def test_fused_equals_separate_c2_subset(R, cache):
 
 
 def test_fused_matches_oracle_binning(R):
-    sc = inputs.config2_scene(n=30_000)
+    sc = inputs.clustered_scene(n=30_000)
     cam = inputs.arc_camera(3, width=320, height=240)
     t = np.float32(0.4)
     ds, fused, sep = renderers(R, sc, 320, 240)
@@ -129,8 +129,8 @@ def test_fused_random_order_counts_per_instance(R):
 
 
 def test_fused_full_size_frame(R):
-    sc = inputs.config2_scene()
-    cams = inputs.config2_cameras()
+    sc = inputs.clustered_scene()
+    cams = inputs.arc_cameras()
     ds, fused, sep = renderers(R, sc, cams[0].width, cams[0].height)
     for j, t in ((10, 0.5), (10, 0.9), (0, 0.1)):
         assert run_both(fused, sep, cams[j], np.float32(t))["num_inst"] > 0
@@ -139,8 +139,8 @@ def test_fused_full_size_frame(R):
 def test_fused_large_image_scans_in_rounds(R):
     """2704 x 2028 has 21,463 tiles: the tile scan adds the counts up first, then scans
     in three rounds of 8,192."""
-    sc = inputs.config2_scene(n=30_000)
-    cam, t = inputs.config5_views()[1]
+    sc = inputs.clustered_scene(n=30_000)
+    cam, t = inputs.large_views()[1]
     ds, fused, sep = renderers(R, sc, cam.width, cam.height)
     assert run_both(fused, sep, cam, t)["num_inst"] > 0
 
@@ -148,7 +148,7 @@ def test_fused_large_image_scans_in_rounds(R):
 def test_fused_overflow_then_a_frame_that_fits(R):
     from paper_2503_22159_amd import binding as B
 
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     near = cam
     far = inputs.look_at((0.0, 0.0, -14.0), width=128, height=128, fovx_deg=60.0)
     i_near = oracle.bin(oracle.project(sc, near, t), near)["I"]
@@ -167,7 +167,7 @@ def test_fused_overflow_then_a_frame_that_fits(R):
 def test_fused_empty_scene(R):
     import torch
 
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     ds, fused, sep = renderers(R, sc.subset(np.arange(0)), cam.width, cam.height)
     fused.project_bin(cam, t)
     img = fused.blend(BG)
@@ -178,7 +178,7 @@ def test_fused_empty_scene(R):
 
 def test_fused_and_separate_calls_share_a_workspace(R):
     """d4dgs_bin_sort leaves the counters zero too, so the calls can alternate."""
-    sc = inputs.config2_scene(n=30_000)
+    sc = inputs.clustered_scene(n=30_000)
     cam = inputs.arc_camera(5, width=320, height=240)
     ds, mixed, ref = renderers(R, sc, 320, 240, cache=False)
     for k, t in enumerate((0.1, 0.4, 0.8, 0.3)):
@@ -205,7 +205,7 @@ def test_uninitialised_workspace_is_reported(R):
 
     from paper_2503_22159_amd import binding as B
 
-    sc = inputs.config2_scene(n=30_000)
+    sc = inputs.clustered_scene(n=30_000)
     cam = inputs.arc_camera(3, width=320, height=240)
     t = np.float32(0.4)
     ds, fused, sep = renderers(R, sc, 320, 240, cache=False)

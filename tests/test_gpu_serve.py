@@ -16,7 +16,7 @@ def env():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_2503_22159_amd import render, serve
 
-    sc = inputs.config4_scene(n=60_000)
+    sc = inputs.serving_scene(n=60_000)
     ds = render.DeviceScene.from_inputs(sc)
     return sc, ds, render, serve
 

@@ -35,7 +35,7 @@ def test_times_equal_single_frames(R, cache):
     again (a camera-cache hit when the cache is on)."""
     import torch
 
-    sc = inputs.config2_scene(n=40_000)
+    sc = inputs.clustered_scene(n=40_000)
     cam = inputs.arc_camera(7, width=337, height=253)
     ds = R.DeviceScene.from_inputs(sc)
     times = [np.float32(k / 19.0) for k in range(20)]
@@ -63,7 +63,7 @@ def test_times_equal_single_frames(R, cache):
 def test_times_frame_against_oracle(R):
     import torch
 
-    sc = inputs.config2_scene(n=40_000)
+    sc = inputs.clustered_scene(n=40_000)
     cam = inputs.arc_camera(3, width=301, height=211)
     ds = R.DeviceScene.from_inputs(sc)
     times = [np.float32(0.0), np.float32(0.35), np.float32(1.0)]
@@ -85,7 +85,7 @@ def test_times_frame_against_oracle(R):
 def test_times_capacity_overflow_is_flagged(R):
     import torch
 
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     ds = R.DeviceScene.from_inputs(sc)
     tr = R.TimesRenderer(ds, cam.width, cam.height, 2, capacity=16, cache=False)
     imgs = tr.render(cam, [t, t], bg=(0.5, 0.25, 0.125))

@@ -130,7 +130,7 @@ def test_flow_single_and_stacked_gaussians_at_centre(oracle_lib):
 
 
 def test_static_scene_has_zero_flow(oracle_lib):
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     sc = sc.subset(np.arange(sc.n))
     sc.velocity[:] = 0.0
     _, _, res = oracle_lib.render(sc, cam, t, flow=True)

@@ -212,7 +212,7 @@ def test_p4_temporal_underflow_contributes_nothing(oracle_lib):
     """A Gaussian whose temporal weight is below 1/255 (tau^2 > 2 ln 255 s_t^2) gets no
     tiles, and adding it leaves the image bit-identical; so does one that is not culled
     but has o w < 1/255 everywhere."""
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     _, _, base = oracle_lib.render(sc, cam, t)
     for extra in (dict(mean=[0, 0, 0], t_mean=[0.9], t_scale=[1e-6], opacity=[0.99]),
                   dict(mean=[0.1, 0, 0], t_mean=[0.0], t_scale=[0.14], opacity=[0.99]),
@@ -284,7 +284,7 @@ def test_p5_slice_first_equivalence(oracle_lib):
 # ------------------------------------------------------------------------------------------- P6
 def test_p6_static_reduction(oracle_lib):
     """v = 0 and s_t -> infinity (w = 1 exactly): the render no longer depends on t."""
-    sc, cam, _ = inputs.config1()
+    sc, cam, _ = inputs.small_case()
     arr = {k: np.asarray(v, np.float64) for k, v in oracle_lib.scene_dict(sc).items()}
     arr["velocity"][:] = 0.0
     arr["t_scale"][:] = 1e30
@@ -338,7 +338,7 @@ def test_p7_depth_orderings_match_product_form(oracle_lib):
 
 # ------------------------------------------------------------------------------------------- P8
 def test_p8_invariants(oracle_lib):
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     proj, bins, res = oracle_lib.render(sc, cam, t)
     T = res["final_T"]
     assert T.min() >= 1e-4 and T.max() <= 1.0
@@ -366,7 +366,7 @@ def test_p8_invariants(oracle_lib):
 
 # ------------------------------------------------------------------------------------------- P9
 def test_p9_binning_bruteforce(oracle_lib):
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     proj = oracle_lib.project(sc, cam, t)
     bins = oracle_lib.bin(proj, cam)
     TX = (cam.width + 15) // 16
@@ -388,7 +388,7 @@ def test_p9_binning_bruteforce(oracle_lib):
 def test_results_independent_of_thread_count(oracle_lib):
     """The oracle's projection, bins and image do not depend on its OpenMP thread count
     (a lazily built shared table once raced under 16 threads)."""
-    sc = inputs.config2_scene(n=4000)
+    sc = inputs.clustered_scene(n=4000)
     cam = inputs.arc_camera(5, width=96, height=80)
     outs = []
     for nt in (1, 3, 16, 0):
@@ -402,9 +402,9 @@ def test_results_independent_of_thread_count(oracle_lib):
 
 
 def test_fp32_and_fp64_decisions_agree(oracle_lib):
-    """The FP32 contract path and the FP64 path take the same tile decisions on config 1
+    """The FP32 contract path and the FP64 path take the same tile decisions on the small case
     (differences could only come from values within rounding of a boundary)."""
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     p32 = oracle_lib.project(sc, cam, t, "f32")
     p64 = oracle_lib.project(sc, cam, t, "f64")
     assert np.array_equal(p32["count"], p64["count"])
@@ -556,7 +556,7 @@ def test_p10_complex_step_projection_matches_fd(oracle_lib):
 def test_p11_transmittance_replay(oracle_lib):
     """Recovering T_i backwards by division reproduces the stored forward T_i (alpha <= 0.99
     bounds the amplification)."""
-    sc, cam, t = inputs.config1()
+    sc, cam, t = inputs.small_case()
     proj, bins, _ = oracle_lib.render(sc, cam, t)
     dL = inputs.upstream_grad(3, cam.width, cam.height)
     g = oracle_lib.blend_bwd(proj, bins, cam, dL)
