@@ -353,6 +353,11 @@ def cpu_baseline(args, scene, cams, times):
     return base, sum(evals) / len(evals)
 
 
+def progress(msg):
+    """One line on stderr as each phase ends (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -379,7 +384,9 @@ def main():
     # the kernel pass: the sweep on one stream, every blend timed by HIP events attached to
     # its launch
     k_elapsed, blend_ms, _ = sweep(args, ds, cams, times, render, 1, True, True)
+    progress(f"kernel pass done ({frames / k_elapsed:.0f} frames/s)")
     elapsed, _, t_host = sweep(args, ds, cams, times, render, max(1, args.streams), False, args.tile_order)
+    progress(f"sweep done ({frames / elapsed:.0f} frames/s)")
     out = {
         "metric": "frames/sec @1352x1014, 300k Gaussians fwd/bwd; serving p50/p99 ms vs plain",
         "value": round(frames / elapsed, 2),
@@ -405,21 +412,27 @@ def main():
     }
     if not args.no_bwd:
         out["fwd_bwd"] = fwd_bwd(args, ds, cams, render, inputs)
+        progress("forward + backward done")
     if not args.no_extras:
         out["sweep_extras"] = side_sweeps(args, ds, cams, times, render)
+        progress("side sweeps done")
     if not args.no_times:
         out["times_batch"] = times_batch(args, ds, cams, render)
+        progress("multi-timestamp batches done")
     if not args.no_steps:
         out["view_steps"] = view_steps(inputs, render)
+        progress("view steps done")
     if not args.no_serve:
         try:
             from paper_2503_22159_amd import serve_bench
 
             out["serving"] = serve_bench.run(seconds=args.serve_seconds)
+            progress("serving done")
         except ImportError:
             out["serving"] = None
     if not args.no_cpu:
         base, mean_evals = cpu_baseline(args, scene, cams, times)
+        progress("CPU oracle done")
         out["cpu_baseline"] = base
         achieved = mean_evals * FLOPS_PER_EVAL / (blend_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "kernel": "k_blend", "achieved": round(achieved, 3),

@@ -15,6 +15,7 @@ requests (all submitted at once) measures the saturated throughput of both.
 """
 from __future__ import annotations
 
+import sys
 import threading
 import time
 
@@ -93,6 +94,7 @@ def run(seconds=10.0, rate=200.0, n=500_000, burst=64, seed=1004):
         res["server"] = _summary(reqs, done, t0)
         res["server"]["burst_frames_per_s"] = _burst(srv, reqs[:burst], outs)
         res["server"]["arena_peak_bytes"] = srv.stats()["arena_peak_bytes"]
+    print(f"serving: server replay done ({len(reqs)} requests)", file=sys.stderr, flush=True)
     with Server.plain(ds) as srv:
         _burst(srv, reqs[:16], outs)
         t0 = time.monotonic_ns() + 20_000_000
