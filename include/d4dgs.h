@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define D4DGS_ABI_VERSION 4
+#define D4DGS_ABI_VERSION 5
 #define D4DGS_TILE 16           /* tile edge in pixels */
 #define D4DGS_CAM_REC_FLOATS 19 /* camera-stage record: p3 u3 covc6 m0_2 md2 rgb3 */
 #define D4DGS_REC_FLOATS 12     /* splat record, 3 x float4 per Gaussian */
@@ -201,9 +201,10 @@ d4dgs_status d4dgs_workspace_size(int32_t n, int32_t width, int32_t height, int6
  * d4dgs_workspace_size), enqueued on `stream`.  d4dgs_project_bin needs them zero when
  * it starts; every d4dgs_project_bin and d4dgs_bin_sort call leaves them zero, so a
  * workspace needs this once, after it is allocated (or after anything else wrote it).
- * Uses hipMemsetAsync: keep it out of captured graphs. */
-d4dgs_status d4dgs_workspace_init(void *workspace, int32_t n, int32_t width, int32_t height, int64_t max_instances,
-                                  d4dgs_stream stream);
+ * INVALID_ARG (nothing written) if workspace_bytes is below what d4dgs_workspace_size
+ * gives for these sizes.  Uses hipMemsetAsync: keep it out of captured graphs. */
+d4dgs_status d4dgs_workspace_init(void *workspace, size_t workspace_bytes, int32_t n, int32_t width, int32_t height,
+                                  int64_t max_instances, d4dgs_stream stream);
 
 /* Camera stage (if `cache` is NULL or misses) and time stage at time t for all
  * scene Gaussians: Alg. 1 camera branch and per-timestamp steps; Eq. 9-15.  Writes

@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libd4dgs.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 MOTION_LINEAR, MOTION_EXACT, MOTION_FROZEN_J = 0, 1, 2  # d4dgs_motion
 TILE = 16
 CAM_REC_FLOATS = 19
@@ -101,7 +101,7 @@ def _load():
         "d4dgs_workspace_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_size_t)]),
         "d4dgs_project": (C.c_int, [C.POINTER(Scene), C.POINTER(Camera), C.c_float, C.POINTER(CamCache),
                                     C.POINTER(Splats), P]),
-        "d4dgs_workspace_init": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, P]),
+        "d4dgs_workspace_init": (C.c_int, [P, C.c_size_t, C.c_int32, C.c_int32, C.c_int32, C.c_int64, P]),
         "d4dgs_project_bin": (C.c_int, [C.POINTER(Scene), C.POINTER(Camera), C.c_float, C.POINTER(CamCache),
                                         C.POINTER(Splats), P, C.c_size_t, C.POINTER(Bins), P, P]),
         "d4dgs_bin_sort": (C.c_int, [C.POINTER(Splats), C.c_int32, C.c_int32, C.c_int32, P, C.c_size_t,

@@ -232,12 +232,14 @@ d4dgs_status d4dgs_project(const d4dgs_scene *scene, const d4dgs_camera *cam, fl
     return project_impl(scene, cam, t, cache, splats, stream, nullptr);
 }
 
-d4dgs_status d4dgs_workspace_init(void *workspace, int32_t n, int32_t width, int32_t height, int64_t max_instances,
-                                  d4dgs_stream stream) {
+d4dgs_status d4dgs_workspace_init(void *workspace, size_t workspace_bytes, int32_t n, int32_t width, int32_t height,
+                                  int64_t max_instances, d4dgs_stream stream) {
     if (!workspace) return fail(D4DGS_ERR_INVALID_ARG, "workspace is NULL");
     if (n < 0 || !image_size_ok(width, height) || max_instances < 1 || max_instances > (int64_t)0x7fffffff)
         return fail(D4DGS_ERR_INVALID_ARG, "workspace sizes out of range");
     const int tiles = ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+    if (workspace_bytes < sort_workspace_bytes(n, max_instances, tiles))
+        return fail(D4DGS_ERR_INVALID_ARG, "workspace_bytes below d4dgs_workspace_size");
     return hip_status(clear_bin_counters(carve_workspace(workspace, n, max_instances, tiles), (hipStream_t)stream),
                       "d4dgs_workspace_init");
 }

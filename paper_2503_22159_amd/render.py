@@ -376,7 +376,8 @@ class Renderer:
         self._cams = {}
         self._bgs = {}
         # the fused projection + binning needs the workspace's tile counters zero once
-        B.check(B.lib.d4dgs_workspace_init(self._ws[0], st.n, self.width, self.height, st.capacity, _stream()))
+        B.check(B.lib.d4dgs_workspace_init(self._ws[0], self._ws[1], st.n, self.width, self.height, st.capacity,
+                                           _stream()))
         torch.cuda.synchronize(dev)
 
     def _cam(self, cam):

@@ -59,9 +59,13 @@ def test_host_argument_checks():
     assert B.lib.d4dgs_serve_create(None, None, None) == B.ERR_INVALID_ARG
     # the fused projection + binning and the workspace initialisation check their
     # arguments before touching the device
-    assert B.lib.d4dgs_workspace_init(None, 10, 64, 64, 1000, None) == B.ERR_INVALID_ARG
-    assert B.lib.d4dgs_workspace_init(C.c_void_p(256), 10, 0, 64, 1000, None) == B.ERR_INVALID_ARG
-    assert B.lib.d4dgs_workspace_init(C.c_void_p(256), 10, 64, 64, 0, None) == B.ERR_INVALID_ARG
+    need = B.workspace_size(10, 64, 64, 1000)
+    assert B.lib.d4dgs_workspace_init(None, need, 10, 64, 64, 1000, None) == B.ERR_INVALID_ARG
+    assert B.lib.d4dgs_workspace_init(C.c_void_p(256), need, 10, 0, 64, 1000, None) == B.ERR_INVALID_ARG
+    assert B.lib.d4dgs_workspace_init(C.c_void_p(256), need, 10, 64, 64, 0, None) == B.ERR_INVALID_ARG
+    # a workspace smaller than d4dgs_workspace_size gives for these sizes
+    assert B.lib.d4dgs_workspace_init(C.c_void_p(256), need - 1, 10, 64, 64, 1000, None) == B.ERR_INVALID_ARG
+    assert b"workspace_bytes" in B.lib.d4dgs_last_error()
     assert B.lib.d4dgs_project_bin(None, None, 0.0, None, None, None, 0, None, None, None) == B.ERR_INVALID_ARG
     s.n, s.sh_degree = 0, 0
     assert B.lib.d4dgs_project_bin(C.byref(s), C.byref(cam), 0.0, None, None, None, 0, None, None,

@@ -219,6 +219,7 @@ def test_uninitialised_workspace_is_reported(R):
         assert not np.any(np.diff(fused.st.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), axis=1))
         assert np.array_equal(img.cpu().numpy(), np.broadcast_to(np.float32(BG)[:, None, None], img.shape))
     st = fused.st
-    B.check(B.lib.d4dgs_workspace_init(C.c_void_p(st.ws.data_ptr()), st.n, 320, 240, st.capacity, R._stream()))
+    B.check(B.lib.d4dgs_workspace_init(C.c_void_p(st.ws.data_ptr()), st.ws.numel(), st.n, 320, 240, st.capacity,
+                                       R._stream()))
     st.status.zero_()
     assert run_both(fused, sep, cam, t)["status"] == 0
