@@ -42,12 +42,20 @@ def build(force=True):
     if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= max(
             os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "oracle_body.inc"))):
         return _LIB_PATH
-    tmp = _LIB_PATH + ".tmp"
+    return compile_library(_HERE, _LIB_PATH)
+
+
+def compile_library(src_dir, out_path):
+    """Compile d4dgs_oracle.c (and the oracle_body.inc it includes) found in src_dir into
+    out_path.  build() uses it on this directory; the mutation tests use it on edited
+    copies of the two files."""
+    tmp = out_path + ".tmp"
     cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-shared", "-fPIC", "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"]
-    subprocess.run(cmd, check=True, cwd=_HERE)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+           "-shared", "-fPIC", "-Wall", "-Wno-unused-function", "-o", tmp,
+           os.path.join(src_dir, "d4dgs_oracle.c"), "-lm"]
+    subprocess.run(cmd, check=True, cwd=src_dir)
+    os.replace(tmp, out_path)
+    return out_path
 
 
 class _Scene(C.Structure):
@@ -66,44 +74,68 @@ class _Camera(C.Structure):
 _lib = None
 
 
+def _load(path):
+    """ctypes handle of an oracle library with its argument types declared."""
+    L = C.CDLL(path)
+    P = C.c_void_p
+    L.oc_version.restype = C.c_int
+    for suf in ("f32", "f64"):
+        f = getattr(L, "oc_project_" + suf)
+        f.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 14
+        f.restype = None
+    L.oc_bin.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, P]
+    L.oc_bin.restype = C.c_int64
+    L.oc_blend.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 12
+    L.oc_blend.restype = C.c_int64
+    L.oc_blend_bruteforce.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 12
+    L.oc_blend_bruteforce.restype = None
+    L.oc_blend_bwd.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 13
+    L.oc_blend_bwd.restype = None
+    L.oc_blend_flow.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 13
+    L.oc_blend_flow.restype = C.c_int64
+    L.oc_blend_bwd_flow.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 16
+    L.oc_blend_bwd_flow.restype = None
+    L.oc_project_bwd.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 6
+    L.oc_project_bwd.restype = None
+    L.oc_project_bwd_flow.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 7
+    L.oc_project_bwd_flow.restype = None
+    L.oc_sh_basis.argtypes = [C.c_int, C.c_int, P, P]
+    L.oc_sh_basis.restype = None
+    L.oc_set_motion.argtypes = [C.c_int]
+    L.oc_set_motion.restype = None
+    L.oc_get_motion.restype = C.c_int
+    L.oc_set_threads.argtypes = [C.c_int]
+    L.oc_set_threads.restype = None
+    L.oc_num_threads.restype = C.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        L = C.CDLL(_LIB_PATH)
-        P = C.c_void_p
-        L.oc_version.restype = C.c_int
-        for suf in ("f32", "f64"):
-            f = getattr(L, "oc_project_" + suf)
-            f.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 14
-            f.restype = None
-        L.oc_bin.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, P]
-        L.oc_bin.restype = C.c_int64
-        L.oc_blend.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 12
-        L.oc_blend.restype = C.c_int64
-        L.oc_blend_bruteforce.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 12
-        L.oc_blend_bruteforce.restype = None
-        L.oc_blend_bwd.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 13
-        L.oc_blend_bwd.restype = None
-        L.oc_blend_flow.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 13
-        L.oc_blend_flow.restype = C.c_int64
-        L.oc_blend_bwd_flow.argtypes = [C.c_int, C.c_int, C.c_int] + [P] * 16
-        L.oc_blend_bwd_flow.restype = None
-        L.oc_project_bwd.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 6
-        L.oc_project_bwd.restype = None
-        L.oc_project_bwd_flow.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 7
-        L.oc_project_bwd_flow.restype = None
-        L.oc_sh_basis.argtypes = [C.c_int, C.c_int, P, P]
-        L.oc_sh_basis.restype = None
-        L.oc_set_motion.argtypes = [C.c_int]
-        L.oc_set_motion.restype = None
-        L.oc_get_motion.restype = C.c_int
-        L.oc_set_threads.argtypes = [C.c_int]
-        L.oc_set_threads.restype = None
-        L.oc_num_threads.restype = C.c_int
-        _lib = L
+        _lib = _load(_LIB_PATH)
     return _lib
+
+
+class variant:
+    """Context manager: every function of this module uses the oracle library at `path`
+    (a build of an edited copy of the sources, see compile_library) until it exits.
+    Test infrastructure for showing that a pin fails under a planted mistake."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.prev = _lib
+        _lib = _load(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.prev
 
 
 MOTION_LINEAR, MOTION_EXACT, MOTION_FROZEN_J = 0, 1, 2

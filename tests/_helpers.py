@@ -3,7 +3,7 @@ and the comparison rules against the oracle."""
 import numpy as np
 
 IMG_TOL = 1e-4          # max-abs on pixels without a near-threshold evaluation
-FLAGGED_TOL = 2e-2      # pixels the oracle flags (alpha near 1/255, T near 1e-4, power near 0)
+FLAGGED_TOL = 1e-2      # pixels the oracle flags (alpha near 1/255, T near 1e-4, power near 0)
 
 
 def decode_record(st, n):
