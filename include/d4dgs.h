@@ -128,7 +128,9 @@ typedef struct {
  *          patterns x0 | y0 << 16 and x1 | y1 << 16 (tiles, half open).  Only written
  *          for Gaussians with count > 0.
  *   count  [n] uint32 tiles touched (0 = culled).
- *   offset [n] uint32 exclusive prefix of count (written by d4dgs_bin_sort).
+ *   offset [n] uint32 exclusive prefix of count (written by d4dgs_bin_sort); 0xffffffff for
+ *          every Gaussian when the binning failed (instance overflow or a workspace whose
+ *          tile counters were not zero), so that d4dgs_render_bwd on such bins adds nothing.
  *   partial [ceil(capacity / 256)] uint32 scratch: per-block sums of count written by
  *          d4dgs_project and turned into block offsets by d4dgs_bin_sort.
  *   mdot   [n][2] floats, optional (NULL: not written): the velocity of the 2D mean at

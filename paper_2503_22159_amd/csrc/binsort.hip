@@ -36,6 +36,7 @@ namespace d4 {
 namespace {
 
 constexpr int kScanThreads = 1024;
+constexpr uint32_t kNoOffset = 0xffffffffu;  // offset of every Gaussian after a failed binning
 constexpr int kSortThreads = 256;
 constexpr int kRankMax = 2 * kSortThreads;  // largest bucket sorted by ranking (two keys per thread)
 static_assert(kSortThreads == kBlock && kSortThreads == kRadix, "one digit counter per thread");
@@ -357,9 +358,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const float4 *__restrict__ r
         build_tile_order(ranges, tiles, TX, order, L.cell, tmp4);
         return;
     }
-    if (misc[1] != 0u) return;  // capacity exceeded (or a bad workspace): nothing downstream runs
-    const uint32_t total = misc[0];
     const int tid = threadIdx.x, gi = blk * kBlock + tid;
+    if (misc[1] != 0u) {
+        // capacity exceeded (or a bad workspace): nothing is emitted and every range is
+        // empty.  An offset past any capacity tells the adjoint that this Gaussian owns no
+        // instance slot (the slots hold nothing of this frame).
+        if (gi < n) offset[gi] = kNoOffset;
+        return;
+    }
+    const uint32_t total = misc[0];
     const uint32_t cnt = gi < n ? count[gi] : 0u;
     const uint32_t excl = block_excl_scan_256(cnt, tmp4);
     if (gi < n) offset[gi] = partial[blk] + excl;

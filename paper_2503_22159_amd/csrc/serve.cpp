@@ -34,6 +34,8 @@ using namespace d4;
 
 namespace {
 
+constexpr int64_t kMaxCapacity = 0x7fffffff;  // instance capacities stay below 2^31 (the scans' range)
+
 int64_t now_ns() {
     return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
         .count();
@@ -256,13 +258,17 @@ bool d4dgs_server::retire_one(Batch &b) {
         const uint32_t status = (uint32_t)(pinned[2 * r->slot + 1] & 0xffffffff);
         r->st.num_instances = ninst;
         inflight_reqs--;
-        if (status == (uint32_t)D4DGS_ERR_CAPACITY) {
+        if (status == (uint32_t)D4DGS_ERR_CAPACITY && ninst > kMaxCapacity) {
+            // more instances than any bins can hold (capacities stay below 2^31)
+            set_error("serve: request has " + std::to_string(ninst) + " tile instances, above 2^31 - 1");
+            finish(r, D4DGS_ERR_CAPACITY);
+        } else if (status == (uint32_t)D4DGS_ERR_CAPACITY) {
             // retry with room for every instance (rounded up), as a new admission
             arena->release(r->off, r->bytes);
             r->bytes = 0;
             free_slots.push_back(r->slot);
             r->slot = -1;
-            r->capacity = std::max<int64_t>(2 * r->capacity, ninst + ninst / 4 + 1024);
+            r->capacity = std::min<int64_t>(std::max<int64_t>(2 * r->capacity, ninst + ninst / 4 + 1024), kMaxCapacity);
             r->retries++;
             stats.retried++;
             pending.push_front(r);
@@ -425,7 +431,7 @@ d4dgs_status d4dgs_serve_submit(d4dgs_server *s, const d4dgs_camera *cam, float 
     r->out = out_img;
     r->capacity = std::max<int64_t>(1 << 16, (int64_t)cam->width * cam->height *
                                                  s->cfg.max_instances_per_pixel_x1000 / 1000);
-    r->capacity = std::min<int64_t>(r->capacity, 0x7fffffff);
+    r->capacity = std::min<int64_t>(r->capacity, kMaxCapacity);
     r->st.submit_ns = now_ns();
     r->st.status = -1;
     *ticket = r->ticket;
