@@ -107,6 +107,8 @@ def _load(path):
     L.oc_set_threads.argtypes = [C.c_int]
     L.oc_set_threads.restype = None
     L.oc_num_threads.restype = C.c_int
+    L.oc_set_flag_margins.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.oc_set_flag_margins.restype = None
     return L
 
 
@@ -158,6 +160,25 @@ class motion:
 
     def __exit__(self, *exc):
         lib().oc_set_motion(self.prev)
+
+
+FLAG_MARGINS = (3e-5, 5e-4, 1e-5)  # default relative margins: alpha near 1/255, T' near 1e-4, power near 0
+
+
+class flag_margins:
+    """Context manager setting the relative margins of the blend's near-threshold flags
+    (alpha near 1/255 or 0.99, T' near 1e-4, exponent near 0).  Bookkeeping only: images
+    and decisions do not change.  For measuring how close FP32 evaluations come."""
+
+    def __init__(self, alpha_rel=FLAG_MARGINS[0], t_rel=FLAG_MARGINS[1], power_rel=FLAG_MARGINS[2]):
+        self.m = (float(alpha_rel), float(t_rel), float(power_rel))
+
+    def __enter__(self):
+        lib().oc_set_flag_margins(*self.m)
+        return self
+
+    def __exit__(self, *exc):
+        lib().oc_set_flag_margins(*FLAG_MARGINS)
 
 
 def set_threads(n):

@@ -38,10 +38,18 @@
 
 /* fp32(2 ln 255): tau^2 > KT * s_t^2  <=>  w < 1/255 (up to rounding) */
 #define OC_KT 11.0825272f
-/* margins inside which an FP32 evaluation may legitimately decide differently */
-#define OC_FLAG_ALPHA_REL 3e-5
-#define OC_FLAG_T_REL 5e-4
-#define OC_FLAG_POWER_REL 1e-5
+/* Relative margins inside which an FP32 evaluation may legitimately decide a threshold
+ * differently from this FP64 blend (flag bookkeeping only: no result depends on them).
+ * Defaults; oc_set_flag_margins changes them for measurements of the FP32 error. */
+static double OC_FLAG_ALPHA_REL = 3e-5;
+static double OC_FLAG_T_REL = 5e-4;
+static double OC_FLAG_POWER_REL = 1e-5;
+void oc_set_flag_margins(double alpha_rel, double t_rel, double power_rel)
+{
+    OC_FLAG_ALPHA_REL = alpha_rel;
+    OC_FLAG_T_REL = t_rel;
+    OC_FLAG_POWER_REL = power_rel;
+}
 
 /* Motion / covariance model of the time stage (the readings of Eq. 13-14 made
  * switchable): 0 = the 2D mean moves linearly (Eq. 13 as printed), Jacobian at the

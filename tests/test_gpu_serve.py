@@ -123,3 +123,41 @@ def test_destroy_with_queued_requests(env):
     assert accepted >= 4 and accepted + busy == len(reqs)
     srv.close()  # cancels what was not admitted, drains what was
     torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def env500():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2503_22159_amd import render, serve
+
+    sc = inputs.serving_scene()  # 500k Gaussians, the serving workload's resident scene
+    return sc, render.DeviceScene.from_inputs(sc), render, serve
+
+
+def test_alone_equals_mix_at_serving_scale(env500):
+    """The serving workload at its real size: 500k Gaussians (SH3) and requests of the
+    seeded stream at 640x480, 1352x1014 and 1920x1080.  32 requests submitted at once
+    (batched, overlapped on 4 streams, 8 GiB budget) give bitwise the images rendered
+    alone through the plain path, and one 1920x1080 request matches the oracle."""
+    import torch
+
+    sc, ds, R, S = env500
+    stream = inputs.serving_requests(duration=2.0)
+    reqs = [(c, t) for _, c, t in stream[:32]]
+    sizes = [(c.width, c.height) for c, _ in reqs]
+    assert {(640, 480), (1352, 1014), (1920, 1080)} <= set(sizes)
+    outs = [torch.full((3, c.height, c.width), float("nan"), device="cuda") for c, _ in reqs]
+    with S.Server(ds, max_inflight=64, max_batch=16, budget_bytes=8 << 30, n_streams=4) as srv:
+        tks = [srv.submit(c, t, o) for (c, t), o in zip(reqs, outs)]
+        stats = [srv.wait(tk) for tk in tks]
+        assert all(s["status"] == 0 for s in stats)
+        assert max(s["batch_size"] for s in stats) > 1, "requests were never batched"
+    torch.cuda.synchronize()
+    for (c, t), o in zip(reqs, outs):
+        alone, _ = R.render_forward(ds, c, t)
+        assert torch.equal(o, alone), (c.width, c.height, float(t))
+    i = sizes.index((1920, 1080))
+    _, _, res = oracle.render(sc, reqs[i][0], reqs[i][1])
+    compare_images(outs[i].cpu().numpy(), None, None, res)
