@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define D4DGS_ABI_VERSION 5
+#define D4DGS_ABI_VERSION 6
 #define D4DGS_TILE 16           /* tile edge in pixels */
 #define D4DGS_CAM_REC_FLOATS 19 /* camera-stage record: p3 u3 covc6 m0_2 md2 rgb3 */
 #define D4DGS_REC_FLOATS 12     /* splat record, 3 x float4 per Gaussian */
@@ -332,6 +332,25 @@ d4dgs_status d4dgs_render_times(const d4dgs_scene *scene, const d4dgs_camera *ca
                                 d4dgs_cam_cache *cache, d4dgs_splats *splats, d4dgs_bins *bins,
                                 void *const *workspace, size_t workspace_bytes, const float bg[3],
                                 float *const *img, int32_t *d_status, d4dgs_stream stream);
+
+/* ------------------------------------------------------ without allocation ------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  d4dgs_bin_sort_noalloc is
+ * d4dgs_bin_sort with its workspace in a static device array of the library,
+ * D4DGS_STATIC_SCRATCH_BYTES (64 MiB) on each GPU the library runs on, held until the
+ * process ends; the call allocates nothing (the array's device address is looked up on
+ * the first call on a GPU).  Arguments, outputs and the device status word are those of
+ * d4dgs_bin_sort, without the workspace.  OUT_OF_MEMORY (nothing enqueued) when
+ * d4dgs_workspace_size(n, width, height, bins->capacity) exceeds
+ * D4DGS_STATIC_SCRATCH_BYTES (e.g. 300k Gaussians at 1352x1014 with 1.2M instances need
+ * about 28 MiB).  All calls on one GPU share its array: calls whose work overlaps on the
+ * device (on streams not ordered against each other) race and give wrong results; calls
+ * ordered on one stream are safe.  The tile counters that must start at zero are cleared
+ * by the call's own first kernel, so what an earlier call left in the array does not
+ * matter. */
+#define D4DGS_STATIC_SCRATCH_BYTES (64u << 20)
+d4dgs_status d4dgs_bin_sort_noalloc(const d4dgs_splats *splats, int32_t n, int32_t width, int32_t height,
+                                    d4dgs_bins *bins, int32_t *d_status, d4dgs_stream stream);
 
 /* ------------------------------------------------------------------ serving ------
  * A server keeps one scene resident and renders requests (camera, t, resolution) as

@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libd4dgs.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 MOTION_LINEAR, MOTION_EXACT, MOTION_FROZEN_J = 0, 1, 2  # d4dgs_motion
 TILE = 16
 CAM_REC_FLOATS = 19
@@ -87,7 +87,7 @@ EXPORTS = ("d4dgs_abi_version", "d4dgs_last_error", "d4dgs_workspace_size", "d4d
            "d4dgs_bin_sort_sync", "d4dgs_render_fwd", "d4dgs_render_fwd_timed", "d4dgs_render_bwd", "d4dgs_serve_create",
            "d4dgs_serve_submit", "d4dgs_serve_poll", "d4dgs_serve_wait", "d4dgs_serve_stats_get",
            "d4dgs_serve_destroy", "d4dgs_render_times", "d4dgs_render_fwd_flow", "d4dgs_flow_loss_workspace_size",
-           "d4dgs_flow_loss", "d4dgs_render_bwd_flow")
+           "d4dgs_flow_loss", "d4dgs_render_bwd_flow", "d4dgs_bin_sort_noalloc")
 
 
 def _load():
@@ -106,6 +106,8 @@ def _load():
                                         C.POINTER(Splats), P, C.c_size_t, C.POINTER(Bins), P, P]),
         "d4dgs_bin_sort": (C.c_int, [C.POINTER(Splats), C.c_int32, C.c_int32, C.c_int32, P, C.c_size_t,
                                      C.POINTER(Bins), P, P]),
+        "d4dgs_bin_sort_noalloc": (C.c_int, [C.POINTER(Splats), C.c_int32, C.c_int32, C.c_int32,
+                                             C.POINTER(Bins), P, P]),
         "d4dgs_bin_sort_sync": (C.c_int, [C.POINTER(Splats), C.c_int32, C.c_int32, C.c_int32, P, C.c_size_t,
                                           C.POINTER(Bins), C.POINTER(C.c_int64), P]),
         "d4dgs_render_fwd": (C.c_int, [C.POINTER(Splats), C.POINTER(Bins), C.c_int32, C.c_int32,
