@@ -162,7 +162,7 @@ class motion:
         lib().oc_set_motion(self.prev)
 
 
-FLAG_MARGINS = (3e-5, 5e-4, 1e-5)  # default relative margins: alpha near 1/255, T' near 1e-4, power near 0
+FLAG_MARGINS = (3e-5, 1e-5, 1e-5)  # default relative margins: alpha near 1/255, T' near 1e-4, power near 0
 
 
 class flag_margins:

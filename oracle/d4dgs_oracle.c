@@ -42,7 +42,7 @@
  * differently from this FP64 blend (flag bookkeeping only: no result depends on them).
  * Defaults; oc_set_flag_margins changes them for measurements of the FP32 error. */
 static double OC_FLAG_ALPHA_REL = 3e-5;
-static double OC_FLAG_T_REL = 5e-4;
+static double OC_FLAG_T_REL = 1e-5;  /* |T' - 1e-4| < 1e-9 */
 static double OC_FLAG_POWER_REL = 1e-5;
 void oc_set_flag_margins(double alpha_rel, double t_rel, double power_rel)
 {
