@@ -39,11 +39,22 @@ FLOPS_PER_EVAL = 22
 ALU_PEAK_TFLOPS = 157.3
 # The same without packed FP32 (the issue-slot bound of the code as compiled).
 ALU_PEAK_NONPACKED_TFLOPS = 78.6
-# HBM bytes per blend launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters, valid only
-# while the blend's sources are the ones the counters were taken with.
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_blend_pmc_traffic_300k_1352x1014.txt")
+# 256 CU x 4 SIMD: a wave64 VALU instruction occupies a SIMD for 4 cycles at 2.4 GHz.
+SIMDS, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4
+# Blend adjoint, per evaluated (pixel, list entry) up to the pixel's last contributor:
+# exponent 11, exp 1, alpha 1, T_i = T / (1 - alpha) 2, g.c 5, dL/dalpha 3, g.S 2,
+# dL/dpower 2, offsets 2 + moments 5, colour gradients 3, the nine sums 9 -> 46 flops.
+FLOPS_PER_BWD_EVAL = 46
+HBM_PEAK_GBS = 8000.0
+# Counter summaries (rocprofv3) of kernels, valid only while the sources they were taken
+# with are unchanged (sources_sha256 in the summary).
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_SUMMARY = os.path.join(PROFILES, "k_blend_pmc_traffic_300k_1352x1014.txt")
 BLEND_SOURCES = ("paper_2503_22159_amd/csrc/blend.hip", "paper_2503_22159_amd/csrc/internal.hpp",
                  "paper_2503_22159_amd/build.py")
+BWD_SUMMARY = os.path.join(PROFILES, "backward_pmc_300k_1352x1014.txt")
+BWD_SOURCES = ("paper_2503_22159_amd/csrc/backward.hip", "paper_2503_22159_amd/csrc/internal.hpp",
+               "paper_2503_22159_amd/build.py")
 
 
 def parse():
@@ -65,37 +76,79 @@ def parse():
                     help="skip the side sweeps (camera cache off, one camera's 300 frames)")
     ap.add_argument("--no-steps", action="store_true",
                     help="skip the 8-view 800x800 (100k, SH1) and 4-view 2704x2028 (2M, SH3) forward+backward steps")
+    ap.add_argument("--view-steps", default="c3,c5",
+                    help="which of those steps to run: c3 (8 x 800x800, 100k SH1), c5 (4 x 2704x2028, 2M SH3)")
     ap.add_argument("--cpu-frames", type=int, default=100)
+    ap.add_argument("--cpu-frames-1core", type=int, default=4, help="frames of the CPU sample timed on one core")
+    ap.add_argument("--bwd-oracle-views", type=int, default=8,
+                    help="views of the backward phase the oracle counts the adjoint's units on")
     ap.add_argument("--bwd-frames", type=int, default=40)
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the 200 req/s serving stream")
+    ap.add_argument("--serve-high-rates", default="2000,6000",
+                    help="arrival rates (req/s, comma separated) of the heavier serving streams ('' : none)")
+    ap.add_argument("--serve-high-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB buffer three times (the reference kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
     return ap.parse_args()
 
 
-def blend_sources_sha256():
+def sources_sha256(sources=BLEND_SOURCES):
     import hashlib
 
     h = hashlib.sha256()
-    for rel in BLEND_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def blend_traffic():
-    """HBM bytes per blend launch from the committed counter summary, or None when there
-    is none or the blend's sources have changed since the counters were taken."""
+def blend_sources_sha256():
+    return sources_sha256(BLEND_SOURCES)
+
+
+def counter_summary(path, sources):
+    """The 'key: value' lines of a committed counter summary, or None when there is none or
+    the kernels' sources have changed since the counters were taken."""
     try:
-        with open(TRAFFIC_SUMMARY) as f:
+        with open(path) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
-        kv = {k.strip(): v.strip() for k, v in kv.items()}
-        if kv.get("sources_sha256") != blend_sources_sha256():
-            return None
-        return float(kv["hbm_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+    except OSError:
         return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    return kv if kv.get("sources_sha256") == sources_sha256(sources) else None
+
+
+def _num(kv, key):
+    try:
+        return float(kv[key]) if kv is not None else None
+    except (KeyError, ValueError):
+        return None
+
+
+def blend_traffic():
+    """HBM bytes per blend launch from the committed counter summary (None if stale)."""
+    return _num(counter_summary(TRAFFIC_SUMMARY, BLEND_SOURCES), "hbm_bytes_per_launch")
+
+
+def issue_frac(valu_insts, seconds):
+    """Share of the SIMDs' VALU issue slots that valu_insts wave instructions fill."""
+    if valu_insts is None or not seconds:
+        return None
+    return valu_insts * CYCLES_PER_VALU / (SIMDS * CLOCK_HZ * seconds)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
 
 
 def copy_calibration():
@@ -108,6 +161,19 @@ def copy_calibration():
         y.copy_(x)
     torch.cuda.synchronize()
     print(f"copy calibration: 3 copies of {4 * n} bytes", file=sys.stderr, flush=True)
+
+
+def scene_order(render, ds_drawn):
+    """The drawn scene stored in the library's spatial order (d4dgs_spatial_order +
+    d4dgs_scene_permute); returns it and the step's time in ms (second of two runs)."""
+    import torch
+
+    render.spatially_ordered(ds_drawn)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ds, _ = render.spatially_ordered(ds_drawn)
+    torch.cuda.synchronize()
+    return ds, 1000.0 * (time.perf_counter() - t0)
 
 
 def touch_streams(k):
@@ -196,7 +262,7 @@ def fwd_bwd(args, ds, cams, render, inputs):
     streams = [torch.cuda.Stream() for _ in range(S)]
     grads = render.grads_like(ds)
     dL = torch.from_numpy(inputs.upstream_grad(7, W, H)).cuda()
-    views = [(cams[(3 * i) % len(cams)], np.float32((i % 10) / 9.0)) for i in range(args.bwd_frames)]
+    views = bwd_views(args, cams)
     bwd_done = [torch.cuda.Event() for _ in range(len(views) + 2)]
 
     def run(vs):
@@ -223,10 +289,46 @@ def fwd_bwd(args, ds, cams, render, inputs):
             "frames": len(views), "camera_cache": False, "streams": S}
 
 
-def side_sweeps(args, ds, cams, times, render):
+def bwd_views(args, cams):
+    import numpy as np
+
+    return [(cams[(3 * i) % len(cams)], np.float32((i % 10) / 9.0)) for i in range(args.bwd_frames)]
+
+
+def bwd_kernel_pass(args, ds, cams, render, inputs):
+    """The backward's two kernels timed on one stream (each alone on the GPU): every view
+    rendered with its replay state, then d4dgs_render_bwd_timed, whose events mark the
+    kernels' own start and end.  Returns their average durations in ms."""
+    import torch
+
+    W, H = cams[0].width, cams[0].height
+    rend = render.Renderer(ds, W, H, capacity=4 * ds.n, cache=False, keep_state=True)
+    grads = render.grads_like(ds)
+    dL = torch.from_numpy(inputs.upstream_grad(7, W, H)).cuda()
+    views = bwd_views(args, cams)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in views]
+    for ev in events:
+        for e in ev:
+            e.record()
+    for cam, t in views[:2]:
+        rend.render(cam, t)
+        rend.backward(cam, t, dL, grads)
+    torch.cuda.synchronize()
+    for (cam, t), ev in zip(views, events):
+        rend.render(cam, t)
+        rend.backward(cam, t, dL, grads, events=ev)
+    torch.cuda.synchronize()
+    assert not rend.overflowed()
+    bb = [ev[0].elapsed_time(ev[1]) for ev in events]
+    pb = [ev[2].elapsed_time(ev[3]) for ev in events]
+    return sum(bb) / len(bb), sum(pb) / len(pb)
+
+
+def side_sweeps(args, ds, cams, times, render, ds_drawn):
     """The headline sweep with the camera-stage cache off (the camera stage then runs for
-    every frame), and one camera's 300 frames alone (camera 10: the analogue of a fixed
-    test view's video), both on the sweep's streams."""
+    every frame), one camera's 300 frames alone (camera 10: the analogue of a fixed test
+    view's video), and the headline sweep on the scene in its drawn order (not spatially
+    ordered), all on the sweep's streams."""
     import types
 
     S = max(1, args.streams)
@@ -234,11 +336,13 @@ def side_sweeps(args, ds, cams, times, render):
     el, _, _ = sweep(off, ds, cams, times, render, S, False, args.tile_order, cache=False)
     one = types.SimpleNamespace(warmup=2, steps=1)
     el1, _, _ = sweep(one, ds, [cams[10]], times, render, S, False, args.tile_order)
+    eld, _, _ = sweep(off, ds_drawn, cams, times, render, S, False, args.tile_order)
     return {"cache_off_frames_per_s": round(len(cams) * len(times) / el, 2),
-            "camera10_frames_per_s": round(len(times) / el1, 2)}
+            "camera10_frames_per_s": round(len(times) / el1, 2),
+            "drawn_order_frames_per_s": round(len(cams) * len(times) / eld, 2)}
 
 
-def view_steps(inputs, render):
+def view_steps(inputs, render, which=("c3", "c5")):
     """Forward + backward steps of the two training-style workloads, on two streams as in
     the forward + backward phase (one view's forward overlaps the previous view's
     backward; the backward passes add into one set of gradients in order):
@@ -249,6 +353,8 @@ def view_steps(inputs, render):
 
     out = {}
     for name in ("c3_8x800x800_100k", "c5_4x2704x2028_2M"):
+        if name[:2] not in which:
+            continue
         if name.startswith("c3"):
             sc, views, _ = inputs.fit_case()
         else:
@@ -334,23 +440,98 @@ def times_batch(args, ds, cams, render):
 
 def cpu_baseline(args, scene, cams, times):
     """The oracle (plain C + OpenMP, FP32 decisions / FP64 blend) on a bounded sample of
-    the timed frames; also returns the oracle's count of blend evaluations."""
+    the timed frames, on all host threads and on one; also returns the oracle's count of
+    blend evaluations per frame and, over a sample of the backward phase's views, the
+    units of the two adjoint kernels (evaluations up to each pixel's last contributor;
+    drawn Gaussians and tile instances)."""
+    import numpy as np
+
     import oracle
 
     oracle.build(force=False)
     n = args.cpu_frames
     # frame j: camera j mod 20 at time index 37 j mod 300 -- spread over the whole sweep
     sample = [(cams[j % len(cams)], times[(37 * j) % len(times)]) for j in range(n)]
+    oracle.set_threads(0)
     evals = []
     t0 = time.perf_counter()
     for cam, t in sample:
         _, _, res = oracle.render(scene, cam, t)
         evals.append(res["n_eval"])
     el = time.perf_counter() - t0
-    base = {"value": round(n / el, 4), "unit": "frames/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    n1 = max(1, args.cpu_frames_1core)
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    for cam, t in sample[:n1]:
+        oracle.render(scene, cam, t)
+    el1 = time.perf_counter() - t1
+    oracle.set_threads(0)
+    base = {"value": round(n / el, 4), "unit": "frames/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} frames of the timed sweep (frame j: camera j mod {len(cams)}, time index "
-                      f"37 j mod {len(times)}); project + bin + blend per frame, {el:.1f} s"}
-    return base, sum(evals) / len(evals)
+                      f"37 j mod {len(times)}); project + bin + blend per frame, {el:.1f} s",
+            "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+            "one_core": {"value": round(n1 / el1, 4), "unit": "frames/s", "cores": 1,
+                         "sample": f"the first {n1} frames of the same sample, {el1:.1f} s"}}
+    bw = {"evals": [], "drawn": [], "instances": []}
+    for cam, t in bwd_views(args, cams)[:args.bwd_oracle_views]:
+        proj, bins, res = oracle.render(scene, cam, t)
+        bw["evals"].append(int(res["n_contrib"].astype(np.int64).sum()))
+        bw["drawn"].append(int((proj["count"] > 0).sum()))
+        bw["instances"].append(int(bins["I"]))
+    bw = {k: sum(v) / len(v) for k, v in bw.items()}
+    return base, sum(evals) / len(evals), bw
+
+
+def blend_roofline(mean_evals, blend_ms):
+    """The dominant kernel's roofline.  achieved: the algorithmic work of Eq. 4 (the
+    oracle's evaluation count x 22 flops) over the blend's live-timed duration -- an
+    effective rate, since the kernel skips the evaluations that cannot reach 1/255.
+    executed: the VALU instructions the kernel issues per launch (committed SQ_INSTS_VALU
+    summary, null once the blend's sources change) as a share of the SIMDs' issue slots
+    over the same duration -- what the hardware does."""
+    sec = blend_ms * 1e-3
+    achieved = mean_evals * FLOPS_PER_EVAL / sec / 1e12
+    kv = counter_summary(TRAFFIC_SUMMARY, BLEND_SOURCES)
+    insts = _num(kv, "sq_insts_valu_per_launch")
+    ifr = issue_frac(insts, sec)
+    return {"bound": "alu", "kernel": "k_blend", "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": blend_traffic(),
+            "basis": "effective: oracle-counted (pixel, list entry) evaluations x 22 flops per live-timed launch",
+            "evals_per_frame": int(mean_evals), "flops_per_eval": FLOPS_PER_EVAL,
+            "peak_nonpacked": ALU_PEAK_NONPACKED_TFLOPS,
+            "frac_nonpacked": round(achieved / ALU_PEAK_NONPACKED_TFLOPS, 4),
+            "executed": {"valu_insts_per_launch": insts, "issue_frac": None if ifr is None else round(ifr, 4),
+                         "source": os.path.relpath(TRAFFIC_SUMMARY, ROOT)}}
+
+
+def backward_rooflines(bw, bwd_ms, sh_degree):
+    """Rooflines of the two adjoint kernels from the one-stream backward pass.
+    k_blend_bwd (ALU): oracle-counted evaluations up to each pixel's last contributor x 46
+    flops per live-timed launch, and its VALU issue share (committed SQ_INSTS_VALU).
+    k_project_bwd (HBM): algorithmic bytes -- per drawn Gaussian its parameters read and its
+    gradients read and written (3 x (16 + 3K) floats), per tile instance the 9 floats of
+    its splat gradient -- per live-timed launch, against 8 TB/s; traffic from the
+    committed FETCH_SIZE / WRITE_SIZE summary (null once the sources change)."""
+    K = (sh_degree + 1) ** 2
+    kv = counter_summary(BWD_SUMMARY, BWD_SOURCES)
+    sb, sp = bwd_ms[0] * 1e-3, bwd_ms[1] * 1e-3
+    ach = bw["evals"] * FLOPS_PER_BWD_EVAL / sb / 1e12
+    insts = _num(kv, "k_blend_bwd_sq_insts_valu_per_launch")
+    ifr = issue_frac(insts, sb)
+    alg = bw["drawn"] * 3 * (16 + 3 * K) * 4 + bw["instances"] * 9 * 4
+    gbs = alg / sp / 1e9
+    return {"k_blend_bwd": {"bound": "alu", "achieved": round(ach, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(ach / ALU_PEAK_TFLOPS, 4), "ms_avg": round(bwd_ms[0], 5),
+                            "evals_per_launch": int(bw["evals"]), "flops_per_eval": FLOPS_PER_BWD_EVAL,
+                            "executed": {"valu_insts_per_launch": insts,
+                                         "issue_frac": None if ifr is None else round(ifr, 4)}},
+            "k_project_bwd": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(gbs / HBM_PEAK_GBS, 4), "ms_avg": round(bwd_ms[1], 5),
+                              "algorithmic_bytes": int(alg), "drawn_per_view": int(bw["drawn"]),
+                              "instances_per_view": int(bw["instances"]),
+                              "traffic": _num(kv, "k_project_bwd_hbm_bytes_per_launch")},
+            "source": os.path.relpath(BWD_SUMMARY, ROOT)}
 
 
 def progress(msg):
@@ -373,8 +554,11 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
-    scene = inputs.clustered_scene()
-    ds = render.DeviceScene.from_inputs(scene)
+    # the scene as drawn (Gaussians of all clusters interleaved), stored on the GPU in the
+    # library's spatial order at load (untimed; its cost is reported)
+    scene = inputs.clustered_scene(morton=False)
+    ds_drawn = render.DeviceScene.from_inputs(scene)
+    ds, order_ms = scene_order(render, ds_drawn)
     cams = inputs.arc_cameras()
     times = [np.float32(k / (args.frames - 1)) for k in range(args.frames)]
     W, H = cams[0].width, cams[0].height
@@ -402,44 +586,50 @@ def main():
         "data": "synthetic",
         "config": {"workload": "300k Gaussians (SH3, 32 clusters), 1352x1014, 20-camera arc x 300 times, "
                                "camera-stage cache on", "frames_per_step": args.frames, "streams": args.streams,
+                   "scene_order": "drawn order, reordered at load by d4dgs_spatial_order",
                    "tile_order": bool(args.tile_order),
                    "binning": "separate" if args.unfused else "fused",
                    "gaussians": scene.n, "width": W, "height": H},
+        "scene_order_ms": round(order_ms, 3),
         "blend_ms_avg": round(blend_ms, 5),
         "kernel_pass": {"streams": 1, "tile_order": True, "frames": frames,
                         "frames_per_s": round(frames / k_elapsed, 2)},
         "host_enqueue_ms_per_frame": round(1000.0 * t_host / frames, 5),
     }
+    bwd_ms = None
     if not args.no_bwd:
         out["fwd_bwd"] = fwd_bwd(args, ds, cams, render, inputs)
+        bwd_ms = bwd_kernel_pass(args, ds, cams, render, inputs)
+        out["fwd_bwd"]["bwd_kernel_pass"] = {"streams": 1, "views": args.bwd_frames,
+                                             "k_blend_bwd_ms_avg": round(bwd_ms[0], 5),
+                                             "k_project_bwd_ms_avg": round(bwd_ms[1], 5)}
         progress("forward + backward done")
     if not args.no_extras:
-        out["sweep_extras"] = side_sweeps(args, ds, cams, times, render)
+        out["sweep_extras"] = side_sweeps(args, ds, cams, times, render, ds_drawn)
         progress("side sweeps done")
     if not args.no_times:
         out["times_batch"] = times_batch(args, ds, cams, render)
         progress("multi-timestamp batches done")
     if not args.no_steps:
-        out["view_steps"] = view_steps(inputs, render)
+        out["view_steps"] = view_steps(inputs, render, args.view_steps.split(","))
         progress("view steps done")
     if not args.no_serve:
         try:
             from paper_2503_22159_amd import serve_bench
 
-            out["serving"] = serve_bench.run(seconds=args.serve_seconds)
+            rates = tuple(float(x) for x in args.serve_high_rates.split(",") if x.strip())
+            out["serving"] = serve_bench.run(seconds=args.serve_seconds, high_rates=rates,
+                                             high_seconds=args.serve_high_seconds)
             progress("serving done")
         except ImportError:
             out["serving"] = None
     if not args.no_cpu:
-        base, mean_evals = cpu_baseline(args, scene, cams, times)
+        base, mean_evals, bw = cpu_baseline(args, scene, cams, times)
         progress("CPU oracle done")
         out["cpu_baseline"] = base
-        achieved = mean_evals * FLOPS_PER_EVAL / (blend_ms * 1e-3) / 1e12
-        out["roofline"] = {"bound": "alu", "kernel": "k_blend", "achieved": round(achieved, 3),
-                           "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                           "traffic": blend_traffic(), "evals_per_frame": int(mean_evals),
-                           "flops_per_eval": FLOPS_PER_EVAL, "peak_nonpacked": ALU_PEAK_NONPACKED_TFLOPS,
-                           "frac_nonpacked": round(achieved / ALU_PEAK_NONPACKED_TFLOPS, 4)}
+        out["roofline"] = blend_roofline(mean_evals, blend_ms)
+        if bwd_ms is not None:
+            out["roofline"]["backward"] = backward_rooflines(bw, bwd_ms, scene.sh_degree)
     print(json.dumps(out), flush=True)
 
 

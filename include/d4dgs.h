@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define D4DGS_ABI_VERSION 6
+#define D4DGS_ABI_VERSION 8
 #define D4DGS_TILE 16           /* tile edge in pixels */
 #define D4DGS_CAM_REC_FLOATS 19 /* camera-stage record: p3 u3 covc6 m0_2 md2 rgb3 */
 #define D4DGS_REC_FLOATS 12     /* splat record, 3 x float4 per Gaussian */
@@ -279,6 +279,16 @@ d4dgs_status d4dgs_render_bwd(const d4dgs_scene *scene, const d4dgs_camera *cam,
                               const float *final_T, const uint32_t *n_contrib, const float *dL_dimg,
                               float *inst_grads, d4dgs_grads *grads, d4dgs_stream stream);
 
+/* d4dgs_render_bwd with its two kernels timed: events (host array of four hipEvent_t,
+ * created by the caller with timing enabled) are set to the start and end of the blend
+ * adjoint (events[0], events[1]) and of the projection adjoint (events[2], events[3]),
+ * the kernels' own execution.  For measurement; the result is that of d4dgs_render_bwd.
+ * INVALID_ARG if any event is NULL. */
+d4dgs_status d4dgs_render_bwd_timed(const d4dgs_scene *scene, const d4dgs_camera *cam, float t,
+                                    const d4dgs_splats *splats, const d4dgs_bins *bins, const float bg[3],
+                                    const float *final_T, const uint32_t *n_contrib, const float *dL_dimg,
+                                    float *inst_grads, d4dgs_grads *grads, void *const *events, d4dgs_stream stream);
+
 /* Optical flow (Sec. 3.3): as d4dgs_render_fwd, and also blends each splat's screen
  * velocity splats->mdot with the colour weights, F = sum_i mdot_i alpha_i T_i (zero
  * behind the last splat), into flow (device) [2][height][width].  splats->mdot must be
@@ -333,6 +343,35 @@ d4dgs_status d4dgs_render_times(const d4dgs_scene *scene, const d4dgs_camera *ca
                                 void *const *workspace, size_t workspace_bytes, const float bg[3],
                                 float *const *img, int32_t *d_status, d4dgs_stream stream);
 
+/* ------------------------------------------------------------ scene order ------
+ * The binning counts a block of 256 consecutive Gaussians with one device atomic per
+ * (block, tile) when the block's Gaussians are close in space, and with one per tile
+ * instance otherwise.  These two calls store a scene in an order that keeps Gaussians
+ * close in space close in memory: a one-time step at scene load (or after
+ * densification), not part of the render path.  The gradients of a reordered scene come
+ * in its order; perm maps them back (gradient j belongs to the caller's Gaussian
+ * perm[j]). */
+typedef struct {
+    float *mean, *scale, *quat, *opacity, *t_mean, *t_scale, *velocity, *sh; /* as d4dgs_scene */
+} d4dgs_scene_arrays;
+
+/* Bytes of scratch d4dgs_spatial_order needs for n Gaussians (n <= 2^30). */
+d4dgs_status d4dgs_spatial_order_workspace_size(int32_t n, size_t *bytes);
+
+/* perm (device, [n] uint32): the Gaussians in ascending 3D Morton (Z-order) code of their
+ * means, ties by index.  The code interleaves, per axis a, the 10-bit cell
+ * floor((mu_a - min_a) / (max_a - min_a) * 1023) (clamped to [0, 1023], float arithmetic,
+ * min / max over the scene's means), x in the lowest bit.  workspace:
+ * d4dgs_spatial_order_workspace_size bytes (device).  Asynchronous on stream. */
+d4dgs_status d4dgs_spatial_order(const d4dgs_scene *scene, uint32_t *perm, void *workspace, size_t workspace_bytes,
+                                 d4dgs_stream stream);
+
+/* dst->x[c][j] = src->x[c][perm[j]] for every parameter array x of the scene (same n and
+ * sh_degree).  perm (device) is any permutation of 0..n-1, e.g. from d4dgs_spatial_order.
+ * dst's arrays are caller-owned device buffers, none of them one of src's.  Asynchronous. */
+d4dgs_status d4dgs_scene_permute(const d4dgs_scene *src, const uint32_t *perm, const d4dgs_scene_arrays *dst,
+                                 d4dgs_stream stream);
+
 /* ------------------------------------------------------ without allocation ------
  * For callers that cannot allocate device memory: code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc.  d4dgs_bin_sort_noalloc is
@@ -367,8 +406,11 @@ typedef struct {
     int64_t scratch_budget_bytes; /* arena size, e.g. 8 GiB */
     int32_t n_streams;            /* e.g. 4 */
     float bg[3];
-    int64_t max_instances_per_pixel_x1000; /* instance capacity per request =
-                                              width * height * this / 1000 (e.g. 1000) */
+    int64_t max_instances_per_pixel_x1000; /* initial instance capacity per request =
+                                              width * height * this / 1000 (e.g. 1000); raised
+                                              to 1.25 x the instances per pixel of the densest
+                                              finished request; a request that overflows is
+                                              rendered again with room for all */
     int32_t max_queue;            /* requests waiting for admission; 0 = 4 * max_inflight */
 } d4dgs_serve_config;
 

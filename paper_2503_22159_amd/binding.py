@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libd4dgs.so")
 
-ABI_VERSION = 6
+ABI_VERSION = 8
 MOTION_LINEAR, MOTION_EXACT, MOTION_FROZEN_J = 0, 1, 2  # d4dgs_motion
 TILE = 16
 CAM_REC_FLOATS = 19
@@ -60,6 +60,10 @@ class Grads(C.Structure):
                                           "split_grad_t", "split_grad_xyz", "split_count")]
 
 
+class SceneArrays(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("mean", "scale", "quat", "opacity", "t_mean", "t_scale", "velocity", "sh")]
+
+
 class ServeConfig(C.Structure):
     _fields_ = [("max_inflight", C.c_int32), ("max_batch", C.c_int32), ("scratch_budget_bytes", C.c_int64),
                 ("n_streams", C.c_int32), ("bg", C.c_float * 3), ("max_instances_per_pixel_x1000", C.c_int64),
@@ -87,7 +91,9 @@ EXPORTS = ("d4dgs_abi_version", "d4dgs_last_error", "d4dgs_workspace_size", "d4d
            "d4dgs_bin_sort_sync", "d4dgs_render_fwd", "d4dgs_render_fwd_timed", "d4dgs_render_bwd", "d4dgs_serve_create",
            "d4dgs_serve_submit", "d4dgs_serve_poll", "d4dgs_serve_wait", "d4dgs_serve_stats_get",
            "d4dgs_serve_destroy", "d4dgs_render_times", "d4dgs_render_fwd_flow", "d4dgs_flow_loss_workspace_size",
-           "d4dgs_flow_loss", "d4dgs_render_bwd_flow", "d4dgs_bin_sort_noalloc")
+           "d4dgs_flow_loss", "d4dgs_render_bwd_flow", "d4dgs_bin_sort_noalloc",
+           "d4dgs_render_bwd_timed", "d4dgs_spatial_order_workspace_size", "d4dgs_spatial_order",
+           "d4dgs_scene_permute")
 
 
 def _load():
@@ -116,6 +122,12 @@ def _load():
                                              C.POINTER(C.c_float * 3), P, P, P, P, P, P]),
         "d4dgs_render_bwd": (C.c_int, [C.POINTER(Scene), C.POINTER(Camera), C.c_float, C.POINTER(Splats),
                                        C.POINTER(Bins), C.POINTER(C.c_float * 3), P, P, P, P, C.POINTER(Grads), P]),
+        "d4dgs_render_bwd_timed": (C.c_int, [C.POINTER(Scene), C.POINTER(Camera), C.c_float, C.POINTER(Splats),
+                                             C.POINTER(Bins), C.POINTER(C.c_float * 3), P, P, P, P, C.POINTER(Grads),
+                                             C.POINTER(C.c_void_p), P]),
+        "d4dgs_spatial_order_workspace_size": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
+        "d4dgs_spatial_order": (C.c_int, [C.POINTER(Scene), P, P, C.c_size_t, P]),
+        "d4dgs_scene_permute": (C.c_int, [C.POINTER(Scene), P, C.POINTER(SceneArrays), P]),
         "d4dgs_serve_create": (C.c_int, [C.POINTER(Scene), C.POINTER(ServeConfig), C.POINTER(C.c_void_p)]),
         "d4dgs_serve_submit": (C.c_int, [P, C.POINTER(Camera), C.c_float, P, C.POINTER(C.c_uint64)]),
         "d4dgs_serve_poll": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(ReqStats)]),

@@ -340,7 +340,8 @@ namespace {
 d4dgs_status render_bwd_impl(const d4dgs_scene *scene, const d4dgs_camera *cam, float t, const d4dgs_splats *splats,
                              const d4dgs_bins *bins, const float bg[3], const float *final_T,
                              const uint32_t *n_contrib, const float *dL_dimg, const float *dL_dflow,
-                             float *inst_grads, d4dgs_grads *grads, d4dgs_stream stream) {
+                             float *inst_grads, d4dgs_grads *grads, d4dgs_stream stream,
+                             void *const *events = nullptr) {
     D4_TRY(check_scene(scene));
     D4_TRY(check_camera(cam));
     D4_TRY(check_splats(splats, scene->n));
@@ -357,14 +358,17 @@ d4dgs_status render_bwd_impl(const d4dgs_scene *scene, const d4dgs_camera *cam, 
         return fail(D4DGS_ERR_INVALID_ARG, "render_bwd: splitting statistics must be all set or all NULL");
     const SceneK sk = make_scenek(*scene);
     const CamK ck = make_camk(*cam);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (events)
+        for (int i = 0; i < 4; ++i) ev[i] = (hipEvent_t)events[i];
     hipError_t e = launch_blend_bwd((const float4 *)splats->rec, splats->offset, bins->values, bins->ranges,
                                     bins->order, ck, bg,
                                     final_T, n_contrib, dL_dimg, dL_dflow ? (const float2 *)splats->mdot : nullptr,
-                                    dL_dflow, (float4 *)inst_grads, bins->capacity, (hipStream_t)stream);
+                                    dL_dflow, (float4 *)inst_grads, bins->capacity, (hipStream_t)stream, ev[0], ev[1]);
     if (e == hipSuccess)
         e = launch_project_bwd(sk, ck, t, (const float4 *)splats->rec, splats->count, splats->offset,
                                (const float4 *)inst_grads, bins->capacity, *grads, splats->motion,
-                               (hipStream_t)stream);
+                               (hipStream_t)stream, ev[2], ev[3]);
     return hip_status(e, "d4dgs_render_bwd");
 }
 
@@ -378,6 +382,16 @@ d4dgs_status d4dgs_render_bwd(const d4dgs_scene *scene, const d4dgs_camera *cam,
                               d4dgs_stream stream) {
     return render_bwd_impl(scene, cam, t, splats, bins, bg, final_T, n_contrib, dL_dimg, nullptr, inst_grads, grads,
                            stream);
+}
+
+d4dgs_status d4dgs_render_bwd_timed(const d4dgs_scene *scene, const d4dgs_camera *cam, float t,
+                                    const d4dgs_splats *splats, const d4dgs_bins *bins, const float bg[3],
+                                    const float *final_T, const uint32_t *n_contrib, const float *dL_dimg,
+                                    float *inst_grads, d4dgs_grads *grads, void *const *events, d4dgs_stream stream) {
+    if (!events || !events[0] || !events[1] || !events[2] || !events[3])
+        return fail(D4DGS_ERR_INVALID_ARG, "render_bwd_timed: four events are needed");
+    return render_bwd_impl(scene, cam, t, splats, bins, bg, final_T, n_contrib, dL_dimg, nullptr, inst_grads, grads,
+                           stream, events);
 }
 
 d4dgs_status d4dgs_render_bwd_flow(const d4dgs_scene *scene, const d4dgs_camera *cam, float t,
@@ -410,6 +424,47 @@ d4dgs_status d4dgs_render_fwd_flow(const d4dgs_splats *splats, const d4dgs_bins 
                                            bins->ranges, bins->order, ck, bg, img, flow, final_T, n_contrib,
                                            (hipStream_t)stream);
     return hip_status(e, "d4dgs_render_fwd_flow");
+}
+
+d4dgs_status d4dgs_spatial_order_workspace_size(int32_t n, size_t *bytes) {
+    if (!bytes) return fail(D4DGS_ERR_INVALID_ARG, "bytes is NULL");
+    if (n < 0 || n > (1 << 30)) return fail(D4DGS_ERR_INVALID_ARG, "spatial_order: n outside [0, 2^30]");
+    *bytes = spatial_order_workspace_bytes(n);
+    return D4DGS_OK;
+}
+
+d4dgs_status d4dgs_spatial_order(const d4dgs_scene *scene, uint32_t *perm, void *workspace, size_t workspace_bytes,
+                                 d4dgs_stream stream) {
+    D4_TRY(check_scene(scene));
+    if (scene->n > (1 << 30)) return fail(D4DGS_ERR_INVALID_ARG, "spatial_order: n above 2^30");
+    if (scene->n > 0 && (!perm || !workspace)) return fail(D4DGS_ERR_INVALID_ARG, "spatial_order: NULL argument");
+    if (workspace_bytes < spatial_order_workspace_bytes(scene->n))
+        return fail(D4DGS_ERR_OUT_OF_MEMORY, "spatial_order: workspace smaller than d4dgs_spatial_order_workspace_size");
+    return hip_status(launch_spatial_order(scene->mean, scene->n, perm, workspace, (hipStream_t)stream),
+                      "d4dgs_spatial_order");
+}
+
+d4dgs_status d4dgs_scene_permute(const d4dgs_scene *src, const uint32_t *perm, const d4dgs_scene_arrays *dst,
+                                 d4dgs_stream stream) {
+    D4_TRY(check_scene(src));
+    if (src->n == 0) return D4DGS_OK;
+    if (!perm || !dst) return fail(D4DGS_ERR_INVALID_ARG, "scene_permute: NULL argument");
+    const float *in[8] = {src->mean, src->scale, src->quat, src->opacity, src->t_mean, src->t_scale, src->velocity,
+                          src->sh};
+    float *out[8] = {dst->mean, dst->scale, dst->quat, dst->opacity, dst->t_mean, dst->t_scale, dst->velocity,
+                     dst->sh};
+    const int K = (src->sh_degree + 1) * (src->sh_degree + 1);
+    const int comps[8] = {3, 3, 4, 1, 1, 1, 3, 3 * K};
+    for (int i = 0; i < 8; ++i) {
+        if (!out[i]) return fail(D4DGS_ERR_INVALID_ARG, "scene_permute: destination array is NULL");
+        for (int k = 0; k < 8; ++k)
+            if ((const float *)out[i] == in[k])
+                return fail(D4DGS_ERR_INVALID_ARG, "scene_permute: a destination array is a source array");
+    }
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 8 && e == hipSuccess; ++i)
+        e = launch_permute(in[i], out[i], perm, src->n, comps[i], (hipStream_t)stream);
+    return hip_status(e, "d4dgs_scene_permute");
 }
 
 d4dgs_status d4dgs_flow_loss_workspace_size(int32_t width, int32_t height, size_t *bytes) {

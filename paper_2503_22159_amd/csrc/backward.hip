@@ -28,6 +28,8 @@
 //               stage (V = R Sigma R^T, Sigma = (Rq S)(Rq S)^T, normalised quaternion,
 //               p = R mu + T, u = R v, spherical-harmonic colour along mu - campos).
 //               Adds into the caller's gradient arrays.
+#include <hip/hip_ext.h>
+
 #include "internal.hpp"
 
 namespace d4 {
@@ -605,33 +607,69 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(SceneK s, CamK c, float 
 
 }  // namespace
 
+// With events e0/e1 each launch goes through hipExtLaunchKernel, which sets them to the
+// kernel's own start and end (for measurement); without work they are recorded together.
 hipError_t launch_blend_bwd(const float4 *rec, const uint32_t *offset, const uint32_t *vals, const uint32_t *ranges,
                             const uint32_t *order, const CamK &c, const float bg[3], const float *final_T, const uint32_t *n_contrib,
                             const float *dL_dimg, const float2 *mdot, const float *dL_dflow, float4 *inst_grads,
-                            int64_t capacity, hipStream_t st) {
+                            int64_t capacity, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int ntiles = c.TX * c.TY;
-    if (ntiles == 0) return hipSuccess;
-    const dim3 grid(tile_grid(c.TX, c.TY, 1));
-    if (mdot && dL_dflow)
-        hipLaunchKernelGGL(k_blend_bwd<true>, grid, dim3(kBwdThreads), 0, st, rec, offset, vals, ranges, order, c, bg[0],
-                           bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, mdot, dL_dflow);
-    else
-        hipLaunchKernelGGL(k_blend_bwd<false>, grid, dim3(kBwdThreads), 0, st, rec, offset, vals, ranges, order, c, bg[0],
-                           bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, (uint32_t)capacity, nullptr,
-                           nullptr);
+    if (ntiles == 0) {
+        if (e0 && hipEventRecord(e0, st) == hipSuccess) (void)hipEventRecord(e1, st);
+        return hipGetLastError();
+    }
+    const dim3 grid(tile_grid(c.TX, c.TY, 1)), block(kBwdThreads);
+    const uint32_t cap = (uint32_t)capacity;
+    if (mdot && dL_dflow) {
+        if (e0)
+            hipExtLaunchKernelGGL(k_blend_bwd<true>, grid, block, 0, st, e0, e1, 0, rec, offset, vals, ranges, order, c,
+                                  bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, cap, mdot, dL_dflow);
+        else
+            hipLaunchKernelGGL(k_blend_bwd<true>, grid, block, 0, st, rec, offset, vals, ranges, order, c, bg[0], bg[1],
+                               bg[2], final_T, n_contrib, dL_dimg, inst_grads, cap, mdot, dL_dflow);
+    } else {
+        const float2 *no_mdot = nullptr;
+        const float *no_dflow = nullptr;
+        if (e0)
+            hipExtLaunchKernelGGL(k_blend_bwd<false>, grid, block, 0, st, e0, e1, 0, rec, offset, vals, ranges, order, c,
+                                  bg[0], bg[1], bg[2], final_T, n_contrib, dL_dimg, inst_grads, cap, no_mdot, no_dflow);
+        else
+            hipLaunchKernelGGL(k_blend_bwd<false>, grid, block, 0, st, rec, offset, vals, ranges, order, c, bg[0], bg[1],
+                               bg[2], final_T, n_contrib, dL_dimg, inst_grads, cap, no_mdot, no_dflow);
+    }
     return hipGetLastError();
 }
 
+namespace {
+
+template <int DEG>
+void launch_project_bwd_deg(const SceneK &s, const CamK &c, float t, const float4 *rec, const uint32_t *count,
+                            const uint32_t *offset, const float4 *inst_grads, uint32_t cap, const d4dgs_grads &g,
+                            int motion, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 grid((s.n + kBlock - 1) / kBlock), block(kBlock);
+    if (e0)
+        hipExtLaunchKernelGGL(k_project_bwd<DEG>, grid, block, 0, st, e0, e1, 0, s, c, t, rec, count, offset,
+                              inst_grads, cap, g, motion);
+    else
+        hipLaunchKernelGGL(k_project_bwd<DEG>, grid, block, 0, st, s, c, t, rec, count, offset, inst_grads, cap, g,
+                           motion);
+}
+
+}  // namespace
+
 hipError_t launch_project_bwd(const SceneK &s, const CamK &c, float t, const float4 *rec, const uint32_t *count,
                               const uint32_t *offset, const float4 *inst_grads, int64_t capacity,
-                              const d4dgs_grads &g, int motion, hipStream_t st) {
-    if (s.n == 0) return hipSuccess;
-    const int grid = (s.n + kBlock - 1) / kBlock;
+                              const d4dgs_grads &g, int motion, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (s.n == 0) {
+        if (e0 && hipEventRecord(e0, st) == hipSuccess) (void)hipEventRecord(e1, st);
+        return hipGetLastError();
+    }
+    const uint32_t cap = (uint32_t)capacity;
     switch (s.deg) {
-        case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g, motion); break;
-        case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g, motion); break;
-        case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g, motion); break;
-        default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(grid), dim3(kBlock), 0, st, s, c, t, rec, count, offset, inst_grads, (uint32_t)capacity, g, motion); break;
+        case 0: launch_project_bwd_deg<0>(s, c, t, rec, count, offset, inst_grads, cap, g, motion, st, e0, e1); break;
+        case 1: launch_project_bwd_deg<1>(s, c, t, rec, count, offset, inst_grads, cap, g, motion, st, e0, e1); break;
+        case 2: launch_project_bwd_deg<2>(s, c, t, rec, count, offset, inst_grads, cap, g, motion, st, e0, e1); break;
+        default: launch_project_bwd_deg<3>(s, c, t, rec, count, offset, inst_grads, cap, g, motion, st, e0, e1); break;
     }
     return hipGetLastError();
 }

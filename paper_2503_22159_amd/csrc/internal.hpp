@@ -290,13 +290,15 @@ hipError_t launch_project(const SceneK &s, const CamK &c, float t, int mode, flo
                           float4 *rec, uint32_t *count, uint32_t *block_sums, float2 *mdot, int motion,
                           hipStream_t st, const BinK *bin = nullptr);
 
-// One request of a batched projection (kernel argument, by value).
+// One request of a batched projection (kernel argument, by value).  bin.cnt_g non-null:
+// the projection also runs the binning's count pass for this request (see BinK).
 struct ReqK {
     CamK cam;
     float t;
     float4 *rec;
     uint32_t *count;
     uint32_t *partial;
+    BinK bin;
 };
 constexpr int kMaxBatch = 16;  // requests per batched-projection launch
 struct BatchArgs {
@@ -362,11 +364,12 @@ hipError_t launch_blend_flow(const float4 *rec, const float2 *mdot, const uint32
                              const uint32_t *order, const CamK &c, const float bg[3], float *img, float *flow, float *final_T,
                              uint32_t *n_contrib, hipStream_t st);
 
-// mdot / dL_dflow NULL: colour only
+// mdot / dL_dflow NULL: colour only; e0/e1 (optional): events set to the kernel's own start and end
 hipError_t launch_blend_bwd(const float4 *rec, const uint32_t *offset, const uint32_t *vals,
                             const uint32_t *ranges, const uint32_t *order, const CamK &c, const float bg[3], const float *final_T,
                             const uint32_t *n_contrib, const float *dL_dimg, const float2 *mdot,
-                            const float *dL_dflow, float4 *inst_grads, int64_t capacity, hipStream_t st);
+                            const float *dL_dflow, float4 *inst_grads, int64_t capacity, hipStream_t st,
+                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 size_t flow_loss_workspace_bytes(int W, int H);
 hipError_t launch_flow_loss(const float *img, const float *flow, int W, int H, float lambda, float eps, void *ws,
@@ -374,7 +377,15 @@ hipError_t launch_flow_loss(const float *img, const float *flow, int W, int H, f
 
 hipError_t launch_project_bwd(const SceneK &s, const CamK &c, float t, const float4 *rec, const uint32_t *count,
                               const uint32_t *offset, const float4 *inst_grads, int64_t capacity,
-                              const d4dgs_grads &g, int motion, hipStream_t st);
+                              const d4dgs_grads &g, int motion, hipStream_t st, hipEvent_t e0 = nullptr,
+                              hipEvent_t e1 = nullptr);
+
+// spatial order of a scene (a one-time step): perm [n]; workspace of
+// spatial_order_workspace_bytes(n)
+size_t spatial_order_workspace_bytes(int n);
+hipError_t launch_spatial_order(const float *mean, int n, uint32_t *perm, void *ws, hipStream_t st);
+// dst[c][j] = src[c][perm[j]], planar [comps][n]
+hipError_t launch_permute(const float *src, float *dst, const uint32_t *perm, int n, int comps, hipStream_t st);
 
 void set_error(const std::string &msg);
 

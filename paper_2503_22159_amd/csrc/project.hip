@@ -319,9 +319,11 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneK s, CamK c, float t, f
 // Batched projection for the server: one thread per Gaussian loads its parameters and
 // covariance once, then runs the camera and time stages for every request of the batch
 // (the same arithmetic as k_project<0>, so each request's record is bit-identical to a
-// single-request projection).
+// single-request projection).  A request with counters (q.bin) also gets the binning's
+// count pass, as in the single-request projection that counts.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_project_batch(SceneK s, BatchArgs args) {
+    __shared__ EmitLds L;
     const int gi = blockIdx.x * kBlock + threadIdx.x;
     const bool valid = gi < s.n;
     GParams<DEG> P;
@@ -336,17 +338,27 @@ __global__ __launch_bounds__(kBlock) void k_project_batch(SceneK s, BatchArgs ar
     }
     for (int r = 0; r < args.nreq; ++r) {
         const ReqK &q = args.r[r];
-        uint32_t cnt = 0;
+        uint32_t cnt = 0, rlo = 0, rhi = 0;
         if (valid && P.ok) {
             CamRec cr;
             camera_stage<DEG>(P, q.cam, cr);
             float4 r0, r1, r2;
             float2 vel;
             cnt = time_stage(cr, op, mut, st, q.t, q.cam, r0, r1, r2, D4DGS_MOTION_LINEAR, vel);
-            if (cnt) store_rec(q.rec, gi, r0, r1, r2);
+            if (cnt) {
+                store_rec(q.rec, gi, r0, r1, r2);
+                rlo = __float_as_uint(r2.z);
+                rhi = __float_as_uint(r2.w);
+            }
         }
         if (valid) q.count[gi] = cnt;
-        block_count_sum(cnt, q.partial);
+        if (q.bin.cnt_g) {  // the same for the whole block
+            emit_count(L, cnt, rlo, rhi, q.bin.TX, blockIdx.x, q.bin.cnt_g, q.bin.cnt_n, q.bin.grp_off,
+                       &q.partial[blockIdx.x]);
+            __syncthreads();  // the next request's count pass rewrites the LDS
+        } else {
+            block_count_sum(cnt, q.partial);
+        }
     }
 }
 

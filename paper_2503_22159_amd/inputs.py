@@ -196,11 +196,12 @@ def small_case():
     return sc, cam, np.float32(0.5)
 
 
-def clustered_scene(n=300_000, seed=2, sh_degree=3):
-    """Plenoptic-like: 32-cluster mixture in [-5,5]^3, SH3."""
+def clustered_scene(n=300_000, seed=2, sh_degree=3, morton=True):
+    """Plenoptic-like: 32-cluster mixture in [-5,5]^3, SH3.  morton=False keeps the draw
+    order (Gaussians of all clusters interleaved, as a trained scene may store them)."""
     return make_scene(seed, n, sh_degree, clusters=32, cluster_box=(-5.0, 5.0), cluster_std=0.8,
                       log_scale=(-4.5, 0.6), dc=(0.5, 0.2), rest_std=0.05,
-                      t_scale_range=(0.02, 0.5), vel_std=0.1)
+                      t_scale_range=(0.02, 0.5), vel_std=0.1, morton=morton)
 
 
 def arc_camera(j, n_cams=20, radius=10.0, width=1352, height=1014):

@@ -69,6 +69,37 @@ class DeviceScene:
         return s
 
 
+def spatial_order(scene: DeviceScene):
+    """perm (int32 [n], device): the library's spatial (3D Morton) order of the scene's
+    Gaussians (d4dgs_spatial_order)."""
+    dev = scene.t["mean"].device
+    perm = torch.empty(max(scene.n, 1), dtype=torch.int32, device=dev)
+    nb = C.c_size_t(0)
+    B.check(B.lib.d4dgs_spatial_order_workspace_size(scene.n, C.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    s = scene.struct()
+    B.check(B.lib.d4dgs_spatial_order(C.byref(s), _ptr(perm), _ptr(ws), ws.numel(), _stream()))
+    return perm[:scene.n]
+
+
+def permute_scene(scene: DeviceScene, perm):
+    """A new DeviceScene holding the scene's Gaussians in the order perm
+    (d4dgs_scene_permute): Gaussian j of the result is Gaussian perm[j] of the input."""
+    out = {k: torch.empty_like(scene.t[k]) for k in FIELDS}
+    a = B.SceneArrays()
+    for k in FIELDS:
+        setattr(a, k, out[k].data_ptr())
+    s = scene.struct()
+    B.check(B.lib.d4dgs_scene_permute(C.byref(s), _ptr(perm), C.byref(a), _stream()))
+    return DeviceScene(out, scene.sh_degree)
+
+
+def spatially_ordered(scene: DeviceScene):
+    """(reordered scene, perm): the scene stored in the library's spatial order."""
+    perm = spatial_order(scene)
+    return permute_scene(scene, perm), perm
+
+
 class FrameState:
     """Device buffers of one rendered frame (splat record, sorted bins, replay state)."""
 
@@ -205,9 +236,12 @@ def grads_like(scene: DeviceScene, split_stats=False):
     return g
 
 
-def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, grads=None, dL_dflow=None):
+def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, grads=None, dL_dflow=None,
+                    events=None):
     """Adds d(sum dL_dimg * img [+ sum dL_dflow * flow])/d(params) into `grads` (created
-    zeroed if None).  dL_dflow needs a frame rendered with the flow."""
+    zeroed if None).  dL_dflow needs a frame rendered with the flow.  events: optional four
+    torch.cuda.Event (timing enabled), set to the start and end of the blend adjoint and
+    of the projection adjoint kernels (colour only)."""
     if grads is None:
         grads = grads_like(scene)
     dL = dL_dimg.contiguous().float()
@@ -220,7 +254,13 @@ def render_backward(scene: DeviceScene, cam, t, bg, st: FrameState, dL_dimg, gra
         if k in grads:
             setattr(g, k, grads[k].data_ptr())
     s = scene.struct()
-    if dL_dflow is None:
+    if dL_dflow is None and events is not None:
+        ev = (C.c_void_p * 4)(*[e.cuda_event for e in events])
+        B.check(B.lib.d4dgs_render_bwd_timed(C.byref(s), C.byref(B.camera_struct(cam)), float(t),
+                                             C.byref(st.splats()), C.byref(st.bins()), C.byref(_bg(bg)),
+                                             _ptr(st.final_T), _ptr(st.n_contrib), _ptr(dL), _ptr(st.inst_grads),
+                                             C.byref(g), ev, _stream()))
+    elif dL_dflow is None:
         B.check(B.lib.d4dgs_render_bwd(C.byref(s), C.byref(B.camera_struct(cam)), float(t), C.byref(st.splats()),
                                        C.byref(st.bins()), C.byref(_bg(bg)), _ptr(st.final_T), _ptr(st.n_contrib),
                                        _ptr(dL), _ptr(st.inst_grads), C.byref(g), _stream()))
@@ -428,13 +468,14 @@ class Renderer:
         self.project_bin(cam, t, stream)
         return self.blend(bg, stream)
 
-    def backward(self, cam, t, dL_dimg, grads, bg=(0.0, 0.0, 0.0)):
-        """Adjoint of the last render() (needs keep_state=True); adds into grads."""
+    def backward(self, cam, t, dL_dimg, grads, bg=(0.0, 0.0, 0.0), events=None):
+        """Adjoint of the last render() (needs keep_state=True); adds into grads.  events:
+        as render_backward."""
         assert self.keep_state
         if getattr(self.st, "inst_grads", None) is None:
             self.st.inst_grads = torch.empty(self.st.capacity * B.GRAD_FLOATS, dtype=torch.float32,
                                              device=self.img.device)
-        return render_backward(self.scene, cam, t, bg, self.st, dL_dimg, grads)
+        return render_backward(self.scene, cam, t, bg, self.st, dL_dimg, grads, events=events)
 
     def overflowed(self):
         """True if any frame since the last reset exceeded the instance capacity."""

@@ -1,17 +1,22 @@
 """Serving measurement: a Poisson stream of render requests against one resident scene.
 
-The request stream follows the serving workload: 500k Gaussians (the clustered scene's distributions,
-SH3) resident on the GPU; arrivals at 200 requests/s; each request a camera on the
-radius-10 sphere, t ~ U[0, 1], resolution 640x480 / 1352x1014 / 1920x1080 with
-probabilities 0.5 / 0.3 / 0.2; at most 64 requests on the GPU, admitted by an 8 GiB
+The request stream follows the serving workload: 500k Gaussians (the clustered scene's
+distributions, SH3) resident on the GPU; arrivals at 200 requests/s for 60 s; each request
+a camera on the radius-10 sphere, t ~ U[0, 1], resolution 640x480 / 1352x1014 / 1920x1080
+with probabilities 0.5 / 0.3 / 0.2; at most 64 requests on the GPU, admitted by an 8 GiB
 scratch budget.  The stream is replayed open-loop (each request is submitted at its
 arrival time regardless of completions) through
 
-  * the continuous-batching server, and
-  * the plain renderer: the same kernels, one request at a time on one stream.
+  * the continuous-batching server (d4dgs_serve_*), and
+  * the plain renderer: in arrival order, each request waits for its arrival time, then
+    d4dgs_project_bin and d4dgs_render_fwd are called in the caller's thread on one
+    stream and the thread waits for them to finish (one request at a time, FIFO).
 
-Latency = completion - scheduled arrival (one monotonic clock).  A closed-loop burst of
-requests (all submitted at once) measures the saturated throughput of both.
+The same two replay heavier streams (2,000 and 6,000 requests/s for 10 s by default; the
+plain renderer's saturated rate is about 6,700 frames/s), where requests arrive while
+others are on the GPU and batches form.  Latency = completion -
+scheduled arrival (one monotonic clock).  A closed-loop burst of requests (all submitted
+at once) measures the saturated throughput of both.
 """
 from __future__ import annotations
 
@@ -40,12 +45,7 @@ def _replay(srv, reqs, outs, t0_ns):
     th = threading.Thread(target=collect)
     th.start()
     for i, (at, cam, t) in enumerate(reqs):
-        target = t0_ns + int(at * 1e9)
-        while True:
-            d = target - time.monotonic_ns()
-            if d <= 0:
-                break
-            time.sleep(min(d, 2_000_000) / 1e9 if d > 300_000 else 0)
+        _wait_until(t0_ns + int(at * 1e9))
         tickets[i] = srv.submit(cam, t, outs[i % len(outs)][(cam.width, cam.height)])
     th.join()
     if err:
@@ -58,10 +58,22 @@ def _summary(reqs, done, t0_ns):
     span = (max(d["done_ns"] for d in done) - t0_ns) / 1e9
     bs = np.array([d["batch_size"] for d in done])
     st = np.array([d["status"] for d in done])
-    return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "mean_ms": round(float(lat.mean()), 3), "max_ms": round(float(lat.max()), 3),
-            "frames_per_s": round(len(done) / span, 2), "requests": len(done),
-            "mean_batch": round(float(bs.mean()), 2), "errors": int((st != 0).sum())}
+    res = {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "mean_ms": round(float(lat.mean()), 3), "max_ms": round(float(lat.max()), 3),
+           "frames_per_s": round(len(done) / span, 2), "requests": len(done),
+           "mean_batch": round(float(bs.mean()), 2), "errors": int((st != 0).sum())}
+    if all("submit_ns" in d for d in done):
+        # where the time goes (p99 of each part): the submit call after the scheduled
+        # arrival (the replaying thread's lateness), waiting for admission and launch, and
+        # the request's own run until completion
+        arr = np.array([t0_ns + int(at * 1e9) for at, _, _ in reqs], np.float64)
+        sub = np.array([d["submit_ns"] for d in done], np.float64)
+        sta = np.array([d["start_ns"] for d in done], np.float64)
+        dn = np.array([d["done_ns"] for d in done], np.float64)
+        res["p99_parts_ms"] = {"late_submit": round(float(np.percentile(sub - arr, 99)) / 1e6, 3),
+                               "queued": round(float(np.percentile(sta - sub, 99)) / 1e6, 3),
+                               "run": round(float(np.percentile(dn - sta, 99)) / 1e6, 3)}
+    return res
 
 
 def _burst(srv, reqs, outs):
@@ -72,7 +84,80 @@ def _burst(srv, reqs, outs):
     return round(len(reqs) / el, 2)
 
 
-def run(seconds=10.0, rate=200.0, n=500_000, burst=64, seed=1004):
+def _wait_until(target_ns):
+    while True:
+        d = target_ns - time.monotonic_ns()
+        if d <= 0:
+            return
+        time.sleep(min(d, 2_000_000) / 1e9 if d > 300_000 else 0)
+
+
+def _plain_renderers(ds, render):
+    """Fixed buffers per resolution of the stream (no camera cache: every request has its
+    own camera)."""
+    from . import inputs
+
+    return {(w, h): render.Renderer(ds, w, h, capacity=4 * ds.n, cache=False) for (w, h) in inputs.RES_CHOICES}
+
+
+def _replay_plain(rends, reqs, t0_ns):
+    """Sequential plain renderer: returns each request's completion time (ns)."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    ev = torch.cuda.Event()
+    done_ns = []
+    for at, cam, t in reqs:
+        _wait_until(t0_ns + int(at * 1e9))
+        rends[(cam.width, cam.height)].render(cam, t)
+        ev.record(stream)
+        while not ev.query():  # poll: a blocking wait adds the runtime's wake-up latency
+            pass
+        done_ns.append(time.monotonic_ns())
+    return done_ns
+
+
+def _plain_summary(reqs, done_ns, t0_ns, rends):
+    done = [{"done_ns": d, "batch_size": 1, "status": 0} for d in done_ns]
+    res = _summary(reqs, done, t0_ns)
+    res["errors"] = sum(int(r.overflowed()) for r in rends.values())  # any capacity overflow
+    return res
+
+
+def _plain_burst(rends, reqs):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _, cam, t in reqs:
+        rends[(cam.width, cam.height)].render(cam, t)
+    torch.cuda.synchronize()
+    return round(len(reqs) / (time.perf_counter() - t0), 2)
+
+
+def _serve_and_plain(ds, render, Server, reqs, outs, burst):
+    res = {}
+    with Server(ds, max_inflight=64, max_batch=16, budget_bytes=8 << 30, n_streams=4) as srv:
+        _burst(srv, reqs[:16], outs)  # warm-up
+        t0 = time.monotonic_ns() + 20_000_000
+        done = _replay(srv, reqs, outs, t0)
+        res["server"] = _summary(reqs, done, t0)
+        res["server"]["burst_frames_per_s"] = _burst(srv, reqs[:burst], outs)
+        st = srv.stats()
+        res["server"]["arena_peak_bytes"] = st["arena_peak_bytes"]
+        res["server"]["retried"] = st["retried"]  # overflowed requests rendered again
+    print(f"serving: server replay done ({len(reqs)} requests)", file=sys.stderr, flush=True)
+    rends = _plain_renderers(ds, render)
+    _plain_burst(rends, reqs[:16])  # warm-up
+    t0 = time.monotonic_ns() + 20_000_000
+    done_ns = _replay_plain(rends, reqs, t0)
+    res["plain"] = _plain_summary(reqs, done_ns, t0, rends)
+    res["plain"]["burst_frames_per_s"] = _plain_burst(rends, reqs[:burst])
+    print(f"serving: plain replay done ({len(reqs)} requests)", file=sys.stderr, flush=True)
+    return res
+
+
+def run(seconds=60.0, rate=200.0, n=500_000, burst=64, seed=1004, high_rates=(2000.0, 6000.0), high_seconds=10.0):
     import torch
 
     from . import inputs, render
@@ -86,20 +171,14 @@ def run(seconds=10.0, rate=200.0, n=500_000, burst=64, seed=1004):
             for _ in range(ring)]
     res = {"workload": f"500k Gaussians SH3 resident, Poisson {rate:g} req/s for {seconds:g} s "
                        f"({len(reqs)} requests), 640x480/1352x1014/1920x1080 @ 0.5/0.3/0.2, "
-                       f"<=64 in flight, 8 GiB scratch"}
-    with Server(ds, max_inflight=64, max_batch=16, budget_bytes=8 << 30, n_streams=4) as srv:
-        _burst(srv, reqs[:16], outs)  # warm-up
-        t0 = time.monotonic_ns() + 20_000_000
-        done = _replay(srv, reqs, outs, t0)
-        res["server"] = _summary(reqs, done, t0)
-        res["server"]["burst_frames_per_s"] = _burst(srv, reqs[:burst], outs)
-        res["server"]["arena_peak_bytes"] = srv.stats()["arena_peak_bytes"]
-    print(f"serving: server replay done ({len(reqs)} requests)", file=sys.stderr, flush=True)
-    with Server.plain(ds) as srv:
-        _burst(srv, reqs[:16], outs)
-        t0 = time.monotonic_ns() + 20_000_000
-        done = _replay(srv, reqs, outs, t0)
-        res["plain"] = _summary(reqs, done, t0)
-        res["plain"]["burst_frames_per_s"] = _burst(srv, reqs[:burst], outs)
+                       f"<=64 in flight, 8 GiB scratch",
+           "plain_renderer": "direct d4dgs_project_bin + d4dgs_render_fwd calls in the caller's thread, "
+                             "one request at a time"}
+    res.update(_serve_and_plain(ds, render, Server, reqs, outs, burst))
+    for k, hr in enumerate(high_rates if high_seconds else ()):
+        hreqs = inputs.serving_requests(rate=hr, duration=high_seconds, seed=seed + 1 + k)
+        res[f"load_{hr:g}_per_s"] = dict(
+            workload=f"Poisson {hr:g} req/s for {high_seconds:g} s ({len(hreqs)} requests), same mix",
+            **_serve_and_plain(ds, render, Server, hreqs, outs, burst))
     torch.cuda.synchronize()
     return res
