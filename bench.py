@@ -363,10 +363,20 @@ def view_steps(inputs, render, which=("c3", "c5")):
         scene_bytes = sum(x.numel() * x.element_size() for x in ds.t.values())
         del sc
         W, H = views[0][0].width, views[0][0].height
+        # instance capacity: 1.25 x the most any view needs (a sizing pass, untimed)
+        probe = render.Renderer(ds, W, H, cache=False)
+        most = 0
+        for cam, t in views:
+            probe.project_bin(cam, t)
+            most = max(most, int(probe.st.num_inst.item()))
+        assert not probe.overflowed()
+        del probe
+        cap = int(1.25 * most) + 1024
         torch.cuda.synchronize()
+        torch.cuda.empty_cache()
         base = torch.cuda.memory_allocated()
         torch.cuda.reset_peak_memory_stats()
-        rends = [render.Renderer(ds, W, H, cache=False, keep_state=True) for _ in range(2)]
+        rends = [render.Renderer(ds, W, H, capacity=cap, cache=False, keep_state=True) for _ in range(2)]
         streams = [torch.cuda.Stream() for _ in range(2)]
         grads = render.grads_like(ds)
         dL = torch.from_numpy(inputs.upstream_grad(11, W, H)).cuda()
