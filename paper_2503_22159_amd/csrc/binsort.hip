@@ -15,16 +15,19 @@
 //                    at its position in the tile's bucket.  (With a tile order, one more
 //                    workgroup sorts the tiles by list length for the launches that
 //                    follow.)
-//   k_tile_sort      one workgroup of 256 per tile sorts its bucket by the 64-bit key --
-//                    depth, ties by Gaussian index: a unique order, so the result does not
-//                    depend on the order the atomics handed out positions.  Buckets of up to
-//                    kRankMax keys are sorted by ranking: the keys are unique, so a key's
-//                    sorted position is the number of smaller keys, counted by each thread
-//                    for its own (up to two) keys while the wavefront streams the bucket
-//                    from LDS, two keys per broadcast read (a bucket of at most 128 keys
-//                    takes one wavefront and no barrier).  Larger buckets: stable
+//   k_tile_sort      one wavefront per tile sorts its bucket by the 64-bit key -- depth,
+//                    ties by Gaussian index: a unique order, so the result does not depend
+//                    on the order the atomics handed out positions.  Up to 64 keys by
+//                    ranking (the keys are unique, so a key's sorted position is the number
+//                    of smaller keys, counted by each lane while the wavefront streams the
+//                    list from LDS); up to 512 keys by ranking inside chunks of 64 and
+//                    merging the chunks by binary search; longer lists by a stable
 //                    least-significant-digit radix sort over the 64 key bits, 8-bit digits,
-//                    ping-ponging between two global scratch arrays.  Writes
+//                    ping-ponging between two global scratch arrays.  A workgroup of one
+//                    wavefront per tile: most lists are short, and wavefronts that a
+//                    larger workgroup would leave idle on them still hold compute-unit
+//                    slots while their tile's range loads (measured: 4 wavefronts per
+//                    tile, 24.9 k sweep frames/s; one, 26.5 k).  Writes
 //                    keys = (tile << 32) | float-bits(depth) and values = gaussian.
 //
 // The instance total lives on the device; no host synchronisation is needed.  If it
@@ -37,9 +40,6 @@ namespace {
 
 constexpr int kScanThreads = 1024;
 constexpr uint32_t kNoOffset = 0xffffffffu;  // offset of every Gaussian after a failed binning
-constexpr int kSortThreads = 256;
-constexpr int kRankMax = 2 * kSortThreads;  // largest bucket sorted by ranking (two keys per thread)
-static_assert(kSortThreads == kBlock && kSortThreads == kRadix, "one digit counter per thread");
 
 __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *tmp4) {
     const int w = threadIdx.x / kWave;
@@ -402,35 +402,126 @@ __device__ __forceinline__ void write_out(uint64_t k, uint32_t pos, uint32_t til
     vals[pos] = (uint32_t)k;
 }
 
-// Stable LSD radix sort of src0[0, s) by all 64 key bits, one workgroup of kSortThreads,
-// 8-bit digits: pass 1 reads src0 and writes a, later passes alternate a -> b -> a, so the
-// eighth pass leaves the result in b.  Elements are ranked in chunks of kSortThreads:
-// within a wavefront by ballot matching on the digit bits, across the wavefronts of the
-// chunk by per-wave digit counts in LDS.
-__device__ void block_radix_sort(const uint64_t *src0, uint64_t *a, uint64_t *b, uint32_t s,
-                                 uint32_t *cnt /* [kRadix] */, uint32_t *wc /* [kSortThreads / kWave][kRadix] */,
-                                 uint32_t *tmp4) {
-    constexpr int NW = kSortThreads / kWave;
-    const int tid = threadIdx.x, w = tid / kWave;
+// Orders the wavefront's LDS (and, with the workgroup being one wavefront, global)
+// accesses before the ones that follow: a barrier of a one-wavefront workgroup.
+__device__ __forceinline__ void wave_step() { __syncthreads(); }
+
+// Number of keys of chunk c of sk (64 keys, sorted or not) below k: 32 broadcast reads of
+// two keys each.
+__device__ __forceinline__ uint32_t chunk_rank(const uint64_t *sk, int c, uint64_t k) {
+    const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(sk + c * kWave);
+    uint32_t r = 0;
+#pragma unroll 8
+    for (int j = 0; j < kWave / 2; ++j) {
+        const ulonglong2 kk = p[j];
+        r += (kk.x < k) + (kk.y < k);
+    }
+    return r;
+}
+
+// Lower bound of k in chunk c of sk once it is sorted: the number of its keys below k (0..64),
+// by binary search (seven dependent broadcast reads).
+__device__ __forceinline__ uint32_t chunk_lower_bound(const uint64_t *sk, int c, uint64_t k) {
+    const uint64_t *o = sk + c * kWave;
+    uint32_t lb = 0;
+#pragma unroll
+    for (int step = kWave / 2; step >= 1; step >>= 1) lb += o[lb + step - 1] < k ? (uint32_t)step : 0u;
+    return lb + (o[lb] < k ? 1u : 0u);
+}
+
+// A list of s <= MAXC * 64 keys, sorted by one wavefront.  Lane l holds keys c * 64 + l
+// (chunk c < nch = ceil(s / 64)); the list is staged in sk with the last chunk padded by ~0
+// (never below a key: a key's high word is a non-negative float's bits).  Each key is
+// ranked inside its chunk (the keys are unique: the rank is the number of the chunk's keys
+// below it) and every chunk is rewritten in sorted order in place; a key's position in the
+// tile's list is then its rank plus, for every other chunk, its lower bound there.  Per key
+// that is 64 comparisons and 7 (nch - 1) probes instead of the s comparisons of ranking
+// against the whole list.  Two chunks are ranked, and two keys searched, side by side, and
+// each key's searches of the other chunks are interleaved, so that the dependent LDS reads
+// overlap.
+template <int MAXC>
+__device__ __forceinline__ void wave_merge_sort(const uint64_t *__restrict__ bucket, uint32_t start, uint32_t s,
+                                                uint64_t *sk, uint32_t tile, uint64_t *__restrict__ keys,
+                                                uint32_t *__restrict__ vals) {
+    static_assert(MAXC % 2 == 0, "chunks go in pairs");
+    const uint32_t ln = lane_id();
+    const int nch = (int)((s + kWave - 1) / kWave);
+    uint64_t k[MAXC];
+    uint32_t r[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+        const uint32_t i = c * kWave + ln;
+        k[c] = c < nch && i < s ? bucket[start + i] : ~0ull;
+        r[c] = ln;  // padding keeps its own slot at the end of the last chunk
+    }
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c)
+        if (c < nch) sk[c * kWave + ln] = k[c];
+    wave_step();
+#pragma unroll
+    for (int c = 0; c < MAXC; c += 2) {
+        if (c >= nch) break;
+        const uint32_t ra = chunk_rank(sk, c, k[c]);
+        const uint32_t rb = c + 1 < nch ? chunk_rank(sk, c + 1, k[c + 1]) : 0u;
+        if (k[c] != ~0ull) r[c] = ra;
+        if (k[c + 1] != ~0ull) r[c + 1] = rb;
+    }
+    wave_step();  // every lane has read every chunk before they are rewritten
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c)
+        if (c < nch) sk[c * kWave + r[c]] = k[c];
+    wave_step();
+#pragma unroll
+    for (int c = 0; c < MAXC; c += 2) {
+        if (c >= nch) break;
+        uint32_t pa = r[c], pb = r[c + 1];
+#pragma unroll
+        for (int d = 0; d < MAXC; ++d) {
+            if (d >= nch) continue;
+            if (d != c) pa += chunk_lower_bound(sk, d, k[c]);
+            if (d != c + 1 && c + 1 < nch) pb += chunk_lower_bound(sk, d, k[c + 1]);
+        }
+        if (c * kWave + ln < s) write_out(k[c], start + pa, tile, keys, vals);
+        if ((c + 1) * kWave + ln < s) write_out(k[c + 1], start + pb, tile, keys, vals);
+    }
+}
+
+// Stable LSD radix sort of src0[0, s) by all 64 key bits, by one wavefront, 8-bit digits:
+// pass 1 reads src0 and writes a, later passes alternate a -> b -> a, so the eighth pass
+// leaves the result in b.  Per pass: the digits counted in LDS (cnt, 256 counters), their
+// exclusive scan (four counters per lane), then the list in chunks of 64 in order, each
+// element placed at its digit's next free slot plus its rank among the chunk's elements of
+// the same digit (ballot matching on the eight digit bits): stable.
+__device__ void wave_radix_sort(const uint64_t *src0, uint64_t *a, uint64_t *b, uint32_t s, uint32_t *cnt) {
+    const uint32_t ln = lane_id();
     const uint64_t lt = lanemask_lt();
     const uint64_t *src = src0;
     uint64_t *dst = a;
     for (int shift = 0; shift < 64; shift += 8) {
-        cnt[tid] = 0u;
-        __syncthreads();
-        for (uint32_t i = tid; i < s; i += kSortThreads) atomicAdd(&cnt[(uint32_t)(src[i] >> shift) & 0xffu], 1u);
-        __syncthreads();
-        const uint32_t c = cnt[tid];
-        const uint32_t e = block_excl_scan_256(c, tmp4);
-        cnt[tid] = e;
-        for (uint32_t r0 = 0; r0 < s; r0 += kSortThreads) {
 #pragma unroll
-            for (int q = 0; q < NW; ++q) wc[q * kRadix + tid] = 0u;
-            __syncthreads();
-            const uint32_t i = r0 + tid;
+        for (int q = 0; q < kRadix / kWave; ++q) cnt[q * kWave + ln] = 0u;
+        wave_step();
+        for (uint32_t i = ln; i < s; i += kWave) atomicAdd(&cnt[(uint32_t)(src[i] >> shift) & 0xffu], 1u);
+        wave_step();
+        uint32_t c4[4], sum = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c4[q] = cnt[4 * ln + q];
+            sum += c4[q];
+        }
+        uint32_t run = wave_incl_scan(sum) - sum;
+        wave_step();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            cnt[4 * ln + q] = run;
+            run += c4[q];
+        }
+        wave_step();
+        for (uint32_t r0 = 0; r0 < s; r0 += kWave) {
+            const uint32_t i = r0 + ln;
             const bool valid = i < s;
-            const uint64_t k = valid ? src[i] : 0ull;
-            const uint32_t d = (uint32_t)(k >> shift) & 0xffu;
+            const uint64_t key = valid ? src[i] : 0ull;
+            const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
             uint64_t peers = __ballot(valid);
 #pragma unroll
             for (int bt = 0; bt < 8; ++bt) {
@@ -438,136 +529,68 @@ __device__ void block_radix_sort(const uint64_t *src0, uint64_t *a, uint64_t *b,
                 const uint64_t bb = __ballot(bit);
                 peers &= bit ? bb : ~bb;
             }
-            const uint32_t rank = __popcll(peers & lt);
-            if (valid && rank == 0) wc[w * kRadix + d] = __popcll(peers);
-            __syncthreads();
-            uint32_t before = 0, total = 0;
-#pragma unroll
-            for (int q = 0; q < NW; ++q) before += q < w ? wc[q * kRadix + d] : 0u;
-            if (valid) dst[cnt[d] + before + rank] = k;
-#pragma unroll
-            for (int q = 0; q < NW; ++q) total += wc[q * kRadix + tid];
-            __syncthreads();
-            cnt[tid] += total;
+            const uint32_t base = cnt[d];
+            if (valid) dst[base + __popcll(peers & lt)] = key;
+            wave_step();  // every lane has read its digit's slot before it moves on
+            if (valid && (peers & lt) == 0ull) cnt[d] = base + __popcll(peers);
+            wave_step();
         }
-        __syncthreads();
         src = dst;
         dst = dst == a ? b : a;
     }
 }
 
-// Number of keys of sk[0, s) below k0 and below k1.  sk is the bucket staged in LDS and
-// padded with ~0 (never below a key: a key's high word is a non-negative float's bits) to
-// an even length, so that it is read two keys per broadcast.
-template <bool TWO>
-__device__ __forceinline__ void rank2(const uint64_t *sk, uint32_t s, uint64_t k0, uint64_t k1, uint32_t &r0,
-                                      uint32_t &r1) {
-    const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(sk);
-    const uint32_t np = (s + 1) >> 1;
-    uint32_t j = 0;
-    for (; j + 4 <= np; j += 4) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const ulonglong2 kk = p[j + q];
-            r0 += (kk.x < k0) + (kk.y < k0);
-            if (TWO) r1 += (kk.x < k1) + (kk.y < k1);
-        }
-    }
-    for (; j < np; ++j) {
-        const ulonglong2 kk = p[j];
-        r0 += (kk.x < k0) + (kk.y < k0);
-        if (TWO) r1 += (kk.x < k1) + (kk.y < k1);
-    }
-}
+// One wavefront per tile.  Lists of up to kWave keys: ranking against the whole list (two
+// keys per broadcast read); up to kMergeMax keys: chunk ranks merged by binary search
+// (wave_merge_sort); longer lists: radix sort.
+constexpr int kMergeMax = 8 * kWave;
+static_assert(kRadix == 4 * kWave, "four digit counters per lane");
 
-// One wavefront sorts a bucket of s <= 64 NQ keys: lane l holds keys l + 64 q (q < NQ),
-// stages them in sk, and ranks them against the whole bucket, two keys per broadcast.
-// Buckets up to kOneWaveMax keys take this path (the other three wavefronts of the
-// workgroup exit at once): fewer resident waves for the same comparisons.  Measured
-// (sweep frames/s): 64 keys 22.7 k, 128 keys 22.9 k, 256 keys 22.6 k.
-constexpr int kOneWaveMax = 128;
-template <int NQ>
 __device__ __forceinline__ void wave_rank_sort(const uint64_t *__restrict__ bucket, uint32_t start, uint32_t s,
                                                uint64_t *sk, uint32_t tile, uint64_t *__restrict__ keys,
                                                uint32_t *__restrict__ vals) {
     const uint32_t ln = lane_id();
-    uint64_t k[NQ];
-    uint32_t r[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const uint32_t i = ln + kWave * q;
-        k[q] = i < s ? bucket[start + i] : ~0ull;
-        r[q] = 0u;
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) sk[ln + kWave * q] = k[q];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t k = ln < s ? bucket[start + ln] : ~0ull;
+    sk[ln] = k;
+    wave_step();
     const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(sk);
-    const uint32_t np = (s + 1) >> 1;
+    const uint32_t np = (s + 1) >> 1;  // an odd list reads the ~0 of lane s as well
+    uint32_t r = 0;
     for (uint32_t j = 0; j < np; ++j) {
         const ulonglong2 kk = p[j];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) r[q] += (kk.x < k[q]) + (kk.y < k[q]);
+        r += (kk.x < k) + (kk.y < k);
     }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const uint32_t i = ln + kWave * q;
-        if (i < s) write_out(k[q], start + r[q], tile, keys, vals);
-    }
+    if (ln < s) write_out(k, start + r, tile, keys, vals);
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_tile_sort(const uint64_t *__restrict__ bucket,
-                                                            uint64_t *__restrict__ alt,
-                                                            const uint32_t *__restrict__ ranges, int tiles,
-                                                            uint64_t *__restrict__ keys,
-                                                            uint32_t *__restrict__ vals,
-                                                            const uint32_t *__restrict__ misc,
-                                                            const uint32_t *__restrict__ order, int TX, int TY) {
+__global__ __launch_bounds__(kWave) void k_tile_sort(const uint64_t *__restrict__ bucket, uint64_t *__restrict__ alt,
+                                                    const uint32_t *__restrict__ ranges, int tiles,
+                                                    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                    const uint32_t *__restrict__ misc,
+                                                    const uint32_t *__restrict__ order, int TX, int TY) {
     if (misc[1] != 0u) return;
-    __shared__ uint32_t cnt[kRadix];
-    __shared__ uint32_t wc[(kSortThreads / kWave) * kRadix];
-    __shared__ uint32_t tmp4[kSortThreads / kWave];
-    __shared__ uint64_t sk[kRankMax];
+    __shared__ uint64_t sk[kMergeMax];
     int tile, unused;
     if (!tile_unit(blockIdx.x, TX, TY, 1, order, tile, unused)) return;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     const uint32_t s = end - start;
-    const uint32_t tid = threadIdx.x;
     if (s == 0) return;
-    if (s <= (uint32_t)kOneWaveMax) {
-        if (tid >= (uint32_t)kWave) return;
-        switch ((s + kWave - 1) / kWave) {
-            case 1: wave_rank_sort<1>(bucket, start, s, sk, (uint32_t)tile, keys, vals); break;
-            default: wave_rank_sort<2>(bucket, start, s, sk, (uint32_t)tile, keys, vals); break;
-        }
-        return;
+    const uint32_t t = (uint32_t)tile;
+    if (s <= (uint32_t)kWave) {
+        wave_rank_sort(bucket, start, s, sk, t, keys, vals);
+    } else if (s <= (uint32_t)(2 * kWave)) {
+        wave_merge_sort<2>(bucket, start, s, sk, t, keys, vals);
+    } else if (s <= (uint32_t)(4 * kWave)) {
+        wave_merge_sort<4>(bucket, start, s, sk, t, keys, vals);
+    } else if (s <= (uint32_t)kMergeMax) {
+        wave_merge_sort<8>(bucket, start, s, sk, t, keys, vals);
+    } else {
+        // 8 radix passes bucket -> alt -> keys -> alt ... -> keys (same index range of each);
+        // the last pass leaves the sorted list in keys, which write_out then rewrites in
+        // place, element by element
+        wave_radix_sort(bucket + start, alt + start, keys + start, s, reinterpret_cast<uint32_t *>(sk));
+        for (uint32_t i = lane_id(); i < s; i += kWave) write_out(keys[start + i], start + i, t, keys, vals);
     }
-    if (s <= (uint32_t)kRankMax) {
-        // the workgroup stages the bucket in LDS (coalesced loads) and every thread ranks
-        // its (up to two) keys against it
-        const uint32_t i1 = tid + kSortThreads;
-        const uint64_t k0 = tid < s ? bucket[start + tid] : ~0ull;
-        const uint64_t k1 = i1 < s ? bucket[start + i1] : ~0ull;
-        sk[tid] = k0;
-        sk[i1] = k1;
-        __syncthreads();
-        if ((tid & ~(uint32_t)(kWave - 1)) >= s) return;  // a wavefront without keys
-        uint32_t r0 = 0, r1 = 0;
-        if (s <= (uint32_t)kSortThreads)
-            rank2<false>(sk, s, k0, k1, r0, r1);
-        else
-            rank2<true>(sk, s, k0, k1, r0, r1);
-        if (tid < s) write_out(k0, start + r0, (uint32_t)tile, keys, vals);
-        if (i1 < s) write_out(k1, start + r1, (uint32_t)tile, keys, vals);
-        return;
-    }
-    // large bucket: 8 radix passes bucket -> alt -> keys -> alt ... -> keys (same index
-    // range of each); the last pass leaves the sorted bucket in keys, which write_out
-    // then rewrites in place, element by element
-    block_radix_sort(bucket + start, alt + start, keys + start, s, cnt, wc, tmp4);
-    for (uint32_t i = tid; i < s; i += kSortThreads) write_out(keys[start + i], start + i, (uint32_t)tile, keys, vals);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -623,7 +646,7 @@ void launch_scatter_sort(const float4 *rec, const uint32_t *count, uint32_t *off
         hipLaunchKernelGGL(k_scatter, dim3(nb + (order ? 1 : 0)), dim3(kBlock), 0, st, rec, count, partial, offset, n,
                            c.TX, (const uint32_t *)ws.misc, (const uint32_t *)ws.grp_off, ws.cur_n, ws.bucket,
                            (const uint32_t *)ranges, tiles, order);
-    hipLaunchKernelGGL(k_tile_sort, dim3(tile_grid(c.TX, c.TY, 1)), dim3(kSortThreads), 0, st,
+    hipLaunchKernelGGL(k_tile_sort, dim3(tile_grid(c.TX, c.TY, 1)), dim3(kWave), 0, st,
                        (const uint64_t *)ws.bucket, ws.alt, ranges, tiles, keys, vals, ws.misc,
                        (const uint32_t *)order, c.TX, c.TY);
 }
