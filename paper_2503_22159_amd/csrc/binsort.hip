@@ -64,8 +64,20 @@ __device__ __forceinline__ bool scan_block_sums(uint32_t *__restrict__ partial, 
     const int tid = threadIdx.x;
     const int per = (nb + kScanThreads - 1) / kScanThreads;
     const int b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
+    // up to kSumsPerThread sums per thread stay in registers between the two passes (all
+    // loads in flight together); more are read again
+    constexpr int kSumsPerThread = 8;
+    const bool held = per <= kSumsPerThread;
+    uint32_t v[kSumsPerThread];
     uint64_t s = 0;
-    for (int i = b0; i < b1; ++i) s += partial[i];
+    if (held) {
+#pragma unroll
+        for (int j = 0; j < kSumsPerThread; ++j) v[j] = b0 + j < b1 ? partial[b0 + j] : 0u;
+#pragma unroll
+        for (int j = 0; j < kSumsPerThread; ++j) s += v[j];
+    } else {
+        for (int i = b0; i < b1; ++i) s += partial[i];
+    }
     const uint64_t inc = wave_incl_scan64(s);
     if (lane_id() == kWave - 1) wsum[tid / kWave] = inc;
     __syncthreads();
@@ -75,10 +87,18 @@ __device__ __forceinline__ bool scan_block_sums(uint32_t *__restrict__ partial, 
         total += wsum[i];
     }
     uint64_t run = base + inc - s;
-    for (int i = b0; i < b1; ++i) {
-        const uint32_t v = partial[i];
-        partial[i] = (uint32_t)min(run, (uint64_t)0xffffffffull);
-        run += v;
+    if (held) {
+#pragma unroll
+        for (int j = 0; j < kSumsPerThread; ++j) {
+            if (b0 + j < b1) partial[b0 + j] = (uint32_t)min(run, (uint64_t)0xffffffffull);
+            run += v[j];
+        }
+    } else {
+        for (int i = b0; i < b1; ++i) {
+            const uint32_t x = partial[i];
+            partial[i] = (uint32_t)min(run, (uint64_t)0xffffffffull);
+            run += x;
+        }
     }
     const bool over = total > (uint64_t)capacity;
     *total_out = total;
@@ -164,17 +184,28 @@ __device__ __forceinline__ uint32_t round_write(const uint32_t (&g)[kScanPer], c
 // Up to kScanThreads * kScanPer tiles (1352 x 1014 has 5,440) take one round: one batch
 // of loads, one barrier.  Larger images add the counts up first (the check needs the
 // total before any range is written), then scan round by round.
+// pre (optional, one-round images only): the counts, already loaded by the caller.
 __device__ __forceinline__ void scan_tiles(uint32_t *__restrict__ cnt_g, uint32_t *__restrict__ cnt_n,
                                            uint32_t *__restrict__ cur_n, int tiles, uint32_t *__restrict__ ranges,
                                            bool over, uint64_t expect, uint32_t *__restrict__ misc,
-                                           int32_t *__restrict__ d_status, TileScanLds &L) {
+                                           int32_t *__restrict__ d_status, TileScanLds &L,
+                                           const uint32_t (*pre_g)[kScanPer] = nullptr,
+                                           const uint32_t (*pre_n)[kScanPer] = nullptr) {
     const int tid = threadIdx.x, w = tid / kWave;
     constexpr int RS = kScanThreads * kScanPer;
     uint32_t g[kScanPer], n[kScanPer], c[kScanPer], inc[kScanPer];
     uint64_t mine = 0;
     const bool one = tiles <= RS;
     if (one) {
-        load_counts(cnt_g, cnt_n, tiles, 0, g, n);
+        if (pre_g) {
+#pragma unroll
+            for (int k = 0; k < kScanPer; ++k) {
+                g[k] = (*pre_g)[k];
+                n[k] = (*pre_n)[k];
+            }
+        } else {
+            load_counts(cnt_g, cnt_n, tiles, 0, g, n);
+        }
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
             mine += (uint64_t)g[k] + n[k];
@@ -256,9 +287,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_both(uint32_t *__restrict
                                                            uint32_t *__restrict__ ranges) {
     __shared__ uint64_t wsum64[kScanThreads / kWave];
     __shared__ TileScanLds L;
+    // an image of one round: its tile counts are loaded first, so that their latency
+    // overlaps the block sums' (the two scans only meet at the capacity check)
+    uint32_t g[kScanPer], n[kScanPer];
+    const bool one = tiles <= kScanThreads * kScanPer;
+    if (one) load_counts(cnt_g, cnt_n, tiles, 0, g, n);
     uint64_t total;
     const bool over = scan_block_sums(partial, nb, capacity, num_inst, misc, d_status, wsum64, &total);
-    scan_tiles(cnt_g, cnt_n, cur_n, tiles, ranges, over, total, misc, d_status, L);
+    if (one)
+        scan_tiles(cnt_g, cnt_n, cur_n, tiles, ranges, over, total, misc, d_status, L, &g, &n);
+    else
+        scan_tiles(cnt_g, cnt_n, cur_n, tiles, ranges, over, total, misc, d_status, L);
 }
 
 // Tile order of the per-tile launches (see tile_unit): the tiles of row class x (rows
