@@ -11,8 +11,9 @@
 //                 dL/dalpha_i = (g.c_i) T_i - (g.S_i) / (1 - alpha_i).
 //               No per-splat forward state is stored.  alpha_i is recomputed by the same
 //               instructions as the forward, so skip decisions match exactly.
-//               Splats whose alpha >= 1/255 box misses the tile are dropped while a batch
-//               is staged (their gradient is zero); the rest are compacted.  Per splat a
+//               Splats that cannot reach alpha >= 1/255 at a pixel of the quadrant
+//               (splat_reaches) are dropped while a batch is staged (their gradient is
+//               zero); the rest are compacted.  Per splat a
 //               lane sums over its pixels dp = dL/dpower and its moments about the splat
 //               mean (dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2; d = pixel - m) and the
 //               three colour gradients; the wave reduces the nine sums with cross-lane
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(FLO
         const uint32_t slot = inst_slot(rec[3 * (size_t)gi + 2], offset[gi], tx, ty);
         if (slot < capacity) zero_slot(ig, slot);  // false only after an instance overflow
     }
-    // staged batch: s2 = {b, bits(plain << 31 | list position), extent x, extent y},
+    // staged batch: s2 = {b, bits(plain << 31 | list position), -, -},
     // s3 = {conic a, b, c, amax}
     __shared__ float4 s0[kWave], s1[kWave], s2[kWave], s3[kWave];
     __shared__ uint32_t sslot[kWave];
@@ -188,8 +189,8 @@ __global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(FLO
             fold_raw(r0, r1, r2, f0, f1, f2);
             s0[ln] = f0;
             s1[ln] = f1;
-            s2[ln] = make_float4(f2.x, __uint_as_float((splat_plain(r0, r1) ? 0x80000000u : 0u) | (j - start)), f2.z,
-                                 f2.w);
+            s2[ln] = make_float4(f2.x, __uint_as_float((splat_plain(r0, r1) ? 0x80000000u : 0u) | (j - start)), 0.0f,
+                                 0.0f);
             s3[ln] = make_float4(r0.z, r0.w, r1.x, r1.y);
             sslot[ln] = inst_slot(r2, offset[gi], tx, ty);
             if (FLOW) s4[ln] = mdot[gi];
@@ -198,8 +199,8 @@ __global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(FLO
         // this quadrant's splats: lane i tests staged splat i
         bool keep = false;
         if ((uint32_t)ln < nb) {
-            const float4 h0 = s0[ln], h2 = s2[ln];
-            keep = !splat_misses(h0, make_float4(0.f, 0.f, h2.z, h2.w), wx0, wx1, wy0, wy1);
+            const float4 h0 = s0[ln];
+            keep = splat_reaches(h0, s1[ln], wx0, wx1, wy0, wy1);
             if (keep) sqc[w][ln] = square_coeffs(h0, s1[ln], xc, yc);
         }
         // sqc[w] is written and read by this wavefront alone (LDS accesses of a wavefront

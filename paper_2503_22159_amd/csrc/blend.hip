@@ -27,8 +27,9 @@ namespace {
 // (ballots of the compares) and applied with inverse ballots.  A done pixel neither blends
 // nor changes: T keeps the transmittance it had before the splat that stopped it.
 //
-// Staging culls: each lane tests its own splat's alpha >= 1/255 box against the wavefront's
-// pixel-centre box and only the splats that can reach one of its pixels are parked, compacted
+// Staging culls: each lane tests whether its own splat can reach alpha >= 1/255 anywhere in
+// the wavefront's pixel-centre box (splat_reaches: the ellipse against the box, exactly up
+// to a margin) and only the splats that can reach one of its pixels are parked, compacted
 // in list order (ballot + lane-rank), so the per-splat loop carries no test.
 // One splat against the lane's PX pixels: g0 = {K, Lx, Ly, qa}, g1 = {qb, qc, r, g},
 // g2 = {b, tag, la, -} (see square_coeffs), md = dm/dt.  PLAIN: the splat passed
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(4 * kWave) void k_blend(const float4 *__restrict__ 
         float4 f0, f1, f2;
         if (j0 + ln < end) {
             fold_raw(n0, n1, n2, f0, f1, f2);
-            keep = !splat_misses(f0, f2, wx0, wx1, wy0, wy1);
+            keep = splat_reaches(f0, f1, wx0, wx1, wy0, wy1);
             plain = splat_plain(n0, n1);
         }
         const uint64_t km = __ballot(keep);

@@ -154,31 +154,11 @@ __device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_lo
 // Over a wavefront's pixel region q is evaluated as a polynomial in the pixel's offset
 // from the region's centre (see square_coeffs).
 //
-// f2.z, f2.w are the half-extents (x, y) of the ellipse where alpha can reach 1/255:
-// amax exp(power) >= 1/255 needs power >= -L, L = ln(255 amax), and -power =
-// 1/2 d^T Q d (Q the conic), so |dx| <= sqrt(2 L Sigma'_xx), |dy| <= sqrt(2 L Sigma'_yy)
-// with Sigma' = Q^-1.  Inflated by 1% + 0.05 px -- far beyond FP32 rounding and the
-// hardware reciprocal / square root used here -- a splat whose box misses every pixel
-// centre of a wavefront is skipped by that whole wavefront without changing any
-// decision: every pixel would have skipped it.  -1 marks a splat that can never reach
-// 1/255 (amax < 1/255).
 __device__ __forceinline__ void fold_raw(const float4 &p, const float4 &q, const float4 &s, float4 &f0, float4 &f1,
                                          float4 &f2) {
     f0 = make_float4(p.x, p.y, (-0.5f * kLog2e) * p.z, (-kLog2e) * p.w);
     f1 = make_float4((-0.5f * kLog2e) * q.x, log2_fast(q.y), q.z, q.w);
-    const float L = (7.99435344f + f1.y) * 0.69314718f;  // ln(255 amax) = (log2 255 + log2 amax) ln 2
-    const float det = p.z * q.x - p.w * p.w;
-    float ex, ey;
-    if (L < -1e-4f) {  // amax clearly below 1/255: no pixel can keep it
-        ex = ey = -1.0f;
-    } else if (det > 0.0f) {
-        const float k2 = 2.0f * fmaxf(L, 0.0f) * __builtin_amdgcn_rcpf(det);
-        ex = __builtin_amdgcn_sqrtf(k2 * q.x) * 1.01f + 0.05f;
-        ey = __builtin_amdgcn_sqrtf(k2 * p.z) * 1.01f + 0.05f;
-    } else {  // conic degenerate in FP32: never skip
-        ex = ey = 3.0e38f;
-    }
-    f2 = make_float4(s.x, q.y, ex, ey);
+    f2 = make_float4(s.x, q.y, 0.0f, 0.0f);
 }
 
 // A splat is "plain" when two of the per-pixel tests cannot fire: its conic is positive
@@ -197,10 +177,35 @@ __device__ __forceinline__ void fold_splat(const float4 *__restrict__ rec, uint3
     fold_raw(rec[3 * (size_t)gi + 0], rec[3 * (size_t)gi + 1], rec[3 * (size_t)gi + 2], f0, f1, f2);
 }
 
-// True if the splat's alpha >= 1/255 box misses the pixel-centre box [x0,x1] x [y0,y1].
-__device__ __forceinline__ bool splat_misses(const float4 &f0, const float4 &f2, float x0, float x1, float y0,
-                                             float y1) {
-    return f2.z < 0.0f || f0.x + f2.z < x0 || f0.x - f2.z > x1 || f0.y + f2.w < y0 || f0.y - f2.w > y1;
+// Whether the splat can reach alpha >= 1/255 at some point of the pixel-centre box
+// [x0,x1] x [y0,y1].  With d = point - m, alpha = amax 2^-P(d), P(d) = A dx^2 + 2B dx dy +
+// C dy^2 (A = -qa, B = -qb / 2, C = -qc: the conic in log2 units), and alpha >= 1/255
+// exactly where P(d) <= log2(255 amax).  For a positive definite P the smallest value over
+// the box is 0 if the box holds the mean; otherwise it lies on a side of the box that faces
+// the mean (from any other boundary point P decreases along a direction that stays in the
+// box), where P is a parabola along the side: the side
+// x = Xn (Xn the box's x-range clamped to 0; Xn = 0 when the range holds 0, which leaves a
+// point of the box) takes its smallest value at y = -B Xn / C clamped to the side, and
+// likewise the side y = Yn.  The smaller of the two values is the minimum.  It is compared
+// with the bound inflated by 1% + 0.01 and by 1e-5 of the terms' magnitude -- far beyond
+// FP32 rounding, the approximate reciprocals and the exponent's own error (1e-4 in log2
+// units) -- so a splat that fails the test is skipped by every pixel of the box without
+// changing any decision.  A conic that is not positive definite with margin is never
+// skipped; amax clearly below 1/255 always is.
+__device__ __forceinline__ bool splat_reaches(const float4 &f0, const float4 &f1, float x0, float x1, float y0,
+                                              float y1) {
+    const float A = -f0.z, B = -0.5f * f0.w, C = -f1.x;
+    const float thr = f1.y + 7.99435344f;  // log2(255 amax)
+    const float X0 = x0 - f0.x, X1 = x1 - f0.x, Y0 = y0 - f0.y, Y1 = y1 - f0.y;
+    const float Xn = __builtin_amdgcn_fmed3f(0.0f, X0, X1), Yn = __builtin_amdgcn_fmed3f(0.0f, Y0, Y1);
+    const float ys = __builtin_amdgcn_fmed3f(-B * Xn * __builtin_amdgcn_rcpf(C), Y0, Y1);
+    const float xs = __builtin_amdgcn_fmed3f(-B * Yn * __builtin_amdgcn_rcpf(A), X0, X1);
+    const float P1 = Xn * (A * Xn + 2.0f * B * ys) + C * ys * ys;
+    const float P2 = xs * (A * xs + 2.0f * B * Yn) + C * Yn * Yn;
+    const float mag = A * (Xn * Xn + xs * xs) + C * (ys * ys + Yn * Yn);
+    const bool pd = A > 0.0f && C > 0.0f && A * C - B * B > 1e-5f * (A * C);
+    if (thr < -0.02f) return false;  // amax clearly below 1/255: no point keeps it
+    return !pd || fminf(P1, P2) <= thr * 1.01f + 0.01f + 1e-5f * mag;
 }
 
 // The exponent over one wavefront's pixel region, expanded about the region's centre
