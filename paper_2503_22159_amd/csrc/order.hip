@@ -53,17 +53,29 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ mean, in
             hi[a] = max(hi[a], o);
         }
     }
+    // wave, then block reduction: one atomic per block and bound (device atomics on the six
+    // words serialise, so the grid is kept to one block per compute unit)
+    __shared__ uint32_t part[6][256 / kWave];
+    const int w = threadIdx.x / kWave;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         lo[a] = wave_min_u32_uniform(lo[a]);
         hi[a] = wave_max_u32_uniform(hi[a]);
-    }
-    if (lane_id() == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(&bb[a], lo[a]);
-            atomicMax(&bb[3 + a], hi[a]);
+        if (lane_id() == 0) {
+            part[a][w] = lo[a];
+            part[3 + a][w] = hi[a];
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        uint32_t v = part[a][0];
+#pragma unroll
+        for (int i = 1; i < 256 / kWave; ++i) v = a < 3 ? min(v, part[a][i]) : max(v, part[a][i]);
+        if (a < 3)
+            atomicMin(&bb[a], v);
+        else
+            atomicMax(&bb[a], v);
     }
 }
 
@@ -175,7 +187,7 @@ hipError_t launch_spatial_order(const float *mean, int n, uint32_t *perm, void *
     uint64_t *keys = (uint64_t *)ws;
     uint32_t *bb = (uint32_t *)((char *)ws + (size_t)n2 * sizeof(uint64_t));
     hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(64), 0, st, bb);
-    hipLaunchKernelGGL(k_bbox, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, mean, n, bb);
+    hipLaunchKernelGGL(k_bbox, dim3(std::min(256, (n + 255) / 256)), dim3(256), 0, st, mean, n, bb);
     hipLaunchKernelGGL(k_morton_keys, dim3((n2 + 255) / 256), dim3(256), 0, st, mean, n, n2, (const uint32_t *)bb,
                        keys);
     const int blocks = n2 / kSortL;
