@@ -12,8 +12,9 @@
  *                     are applied after the spatial projection).
  *   d4dgs_bin_sort    tile binning of the projected splats and a depth-keyed sort of
  *                     each tile's list, front to back (the tiled rasteriser the paper
- *                     adopts from 3D Gaussian Splatting, Sec. 3.2.2): keys of up to 512
- *                     per tile are ranked, longer lists radix-sorted.
+ *                     adopts from 3D Gaussian Splatting, Sec. 3.2.2): one wavefront per
+ *                     tile ranks lists of up to 512 keys (in chunks of 64, merged by
+ *                     binary search) and radix-sorts longer ones.
  *   d4dgs_project_bin d4dgs_project + d4dgs_bin_sort with the binning's counting done
  *                     by the projection (fewer launches per frame; same output).
  *   d4dgs_render_fwd  per-tile front-to-back alpha blending, Eq. 4.
@@ -26,6 +27,11 @@
  *   d4dgs_render_fwd_flow, d4dgs_flow_loss, d4dgs_render_bwd_flow
  *                     the rendered optical flow and the flow-gradient guided
  *                     consistency loss (Sec. 3.3, Eq. 16-17) with their adjoints.
+ *   d4dgs_spatial_order, d4dgs_scene_permute
+ *                     a one-time reorder of a scene along a 3D Morton curve, which the
+ *                     binning's per-(block, tile) counting relies on.
+ *   d4dgs_bin_sort_noalloc
+ *                     d4dgs_bin_sort with its workspace in a static device array.
  *
  * Conventions
  *  - Every pointer marked (device) is device memory owned by the caller; the library
@@ -393,13 +399,14 @@ d4dgs_status d4dgs_bin_sort_noalloc(const d4dgs_splats *splats, int32_t n, int32
 
 /* ------------------------------------------------------------------ serving ------
  * A server keeps one scene resident and renders requests (camera, t, resolution) as
- * they arrive.  Requests are admitted while fewer than max_inflight are on the GPU and
- * their scratch fits the free part of the arena (scratch_budget_bytes, reserved at
- * creation); admitted requests are grouped into batches whose projection runs as one
- * launch over (request x Gaussian); batches run on n_streams streams so that one
- * batch's blending overlaps the next batch's projection.  A request's image is
- * bitwise the same whether it is rendered alone or in a batch.  submit/poll/wait/
- * stats are thread-safe. */
+ * they arrive.  Requests are admitted in arrival order while fewer than max_inflight are
+ * on the GPU and their scratch fits the free part of the arena (scratch_budget_bytes,
+ * reserved at creation); the requests admitted together form a batch whose projection
+ * runs as one launch over (request x Gaussian), and each request then bins and blends on
+ * the least loaded of n_streams streams and completes on its own (an event per request),
+ * so requests that arrive while others run overlap them on the device.  A request's
+ * image is bitwise the same whether it is rendered alone or in a batch.  submit/poll/
+ * wait/stats are thread-safe. */
 typedef struct {
     int32_t max_inflight;         /* requests on the GPU at once, e.g. 64 */
     int32_t max_batch;            /* requests per batch, <= max_inflight */
