@@ -199,17 +199,22 @@ def touch_streams(k):
 def sweep(args, ds, cams, times, render, S, time_blends, tile_order, streams=None, cache=True):
     """The camera-major sweep: `args.warmup` untimed steps, then `args.steps` timed ones.
     Frames are independent, so consecutive frames go round-robin to S HIP streams
-    (default priority), each with its own frame buffers and camera-stage cache: one
-    frame's binning overlaps another's blend.  With time_blends, every blend kernel is
-    launched with a pair of HIP events (created and first recorded beforehand) that the
-    launch sets to the kernel's own start and end; the benchmark does that on one
-    stream, so that no other stream's kernels share the compute units meanwhile."""
+    (default priority), each with its own frame buffers: one frame's binning overlaps
+    another's blend.  The streams share one camera-stage cache, so the camera stage runs
+    once per camera (Alg. 1); a camera's first frame fills it after the other streams'
+    frames of the previous camera, and their frames of the new camera wait for it
+    (render.SharedCameraOrder).  With time_blends, every blend kernel is launched with a
+    pair of HIP events (created and first recorded beforehand) that the launch sets to the
+    kernel's own start and end; the benchmark does that on one stream, so that no other
+    stream's kernels share the compute units meanwhile."""
     import torch
 
     W, H = cams[0].width, cams[0].height
-    rends = [render.Renderer(ds, W, H, capacity=4 * ds.n, cache=cache, tile_order=tile_order) for _ in range(S)]
+    shared = render.CamCache(ds.n) if cache else False
+    rends = [render.Renderer(ds, W, H, capacity=4 * ds.n, cache=shared, tile_order=tile_order) for _ in range(S)]
     streams = streams or [torch.cuda.Stream() for _ in range(S)]
     handles = [st.cuda_stream for st in streams]
+    order = render.SharedCameraOrder(streams) if cache else None
     nfr = len(times)
     events = []
     if time_blends:
@@ -221,16 +226,24 @@ def sweep(args, ds, cams, times, render, S, time_blends, tile_order, streams=Non
 
     fused = not getattr(args, "unfused", False)
 
+    last = [None]
+
     def step(k, ev):
         cam = cams[k % len(cams)]
+        miss = cam is not last[0]  # the cache misses on the first frame of a new camera
+        last[0] = cam
         for i, t in enumerate(times):
             r = i % S
             rend, h = rends[r], handles[r]
+            if order:
+                order.before_miss(r) if (miss and i == 0) else order.before_hit(r)
             if fused:
                 rend.project_bin(cam, t, h)
             else:
                 rend.project(cam, t, h)
                 rend.bin_sort(h)
+            if order and miss and i == 0:
+                order.after_miss(r)
             rend.blend(stream=h, events=ev[i] if ev else None)
 
     for k in range(args.warmup):
@@ -596,6 +609,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "300k Gaussians (SH3, 32 clusters), 1352x1014, 20-camera arc x 300 times, "
                                "camera-stage cache on", "frames_per_step": args.frames, "streams": args.streams,
+                   "camera_cache": "one, shared by the streams (camera stage once per camera)",
                    "scene_order": "drawn order, reordered at load by d4dgs_spatial_order",
                    "tile_order": bool(args.tile_order),
                    "binning": "separate" if args.unfused else "fused",

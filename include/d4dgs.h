@@ -113,7 +113,11 @@ typedef struct {
 /* Camera-stage cache (Alg. 1: the camera branch runs only when the camera changes).
  * `rec` (device) holds D4DGS_CAM_REC_FLOATS * capacity floats, planar
  * [p.xyz, u.xyz, covc(00,01,02,11,12,22), m0.xy, md.xy, rgb][capacity].  The library
- * fills the other fields; set `valid` to 0 after changing the scene's parameters. */
+ * fills the other fields; set `valid` to 0 after changing the scene's parameters.
+ * A call hits or misses on the host, when it is made; a miss writes `rec` on the
+ * call's stream.  One cache may serve calls on several streams (frames of one camera
+ * rendered concurrently): the caller then orders a missing call after the other
+ * streams' earlier calls with the cache, and their later calls after it (events). */
 typedef struct {
     float *rec;
     int32_t capacity;

@@ -160,6 +160,38 @@ class CamCache:
         self.c.valid = 0
 
 
+class SharedCameraOrder:
+    """Stream ordering for one CamCache shared by renderers on several streams.
+
+    The cache is hit or missed on the host, when a call is made; its record is written on
+    the device by the missing call's camera stage.  So a miss (the first frame of a camera)
+    must run after every frame the other streams have queued, which may still read the
+    previous camera's record, and the other streams' frames of the new camera must run
+    after the miss has written it: before_miss / after_miss around the call that misses,
+    before_hit before every other call (it waits once per stream and camera)."""
+
+    def __init__(self, streams):
+        self.streams = list(streams)
+        self.fill = torch.cuda.Event()
+        self.read = [torch.cuda.Event() for _ in self.streams]
+        self.waited = [True] * len(self.streams)
+
+    def before_miss(self, s):
+        for q, st in enumerate(self.streams):
+            if q != s:
+                self.read[q].record(st)
+                self.streams[s].wait_event(self.read[q])
+
+    def after_miss(self, s):
+        self.fill.record(self.streams[s])
+        self.waited = [q == s for q in range(len(self.streams))]
+
+    def before_hit(self, s):
+        if not self.waited[s]:
+            self.streams[s].wait_event(self.fill)
+            self.waited[s] = True
+
+
 def _bg(bg):
     a = (C.c_float * 3)()
     for i in range(3):
@@ -393,12 +425,17 @@ class Renderer:
 
     def __init__(self, scene: DeviceScene, width, height, capacity=None, cache=True, keep_state=False,
                  tile_order=True):
+        """cache: True (a camera-stage cache of its own), False, or a CamCache shared with
+        other renderers (on other streams: see SharedCameraOrder)."""
         self.scene = scene
         self.width, self.height = int(width), int(height)
         dev = scene.t["mean"].device
         self.st = FrameState(scene.n, self.width, self.height,
                              capacity or default_capacity(scene.n, width, height), dev, tile_order=tile_order)
-        self.cache = CamCache(scene.n, dev) if cache else None
+        if isinstance(cache, CamCache):
+            self.cache = cache
+        else:
+            self.cache = CamCache(scene.n, dev) if cache else None
         self.keep_state = keep_state
         self.img = torch.empty((3, self.height, self.width), dtype=torch.float32, device=dev)
         if keep_state:
@@ -408,7 +445,7 @@ class Renderer:
         self._scene_s = scene.struct()
         self._sp = st.splats()
         self._bn = st.bins()
-        self._cache_p = C.byref(self.cache.c) if cache else None
+        self._cache_p = C.byref(self.cache.c) if self.cache is not None else None
         self._ws = (_ptr(st.ws), st.ws.numel())
         self._status = _ptr(st.status)
         self._img = _ptr(self.img)

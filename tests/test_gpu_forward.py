@@ -83,17 +83,33 @@ def test_c2_full_size_frame(R):
     print("c2 full", stats)
 
 
-@pytest.mark.parametrize("n", [150, 300, 1200, 3000])
-def test_dense_tiles_every_sort_path(R, n):
-    """Large splats over a 48x48 view (9 tiles): every Gaussian lands in every tile, so the
-    buckets hold ~1.2 n keys and take each per-tile sort (ranking up to 512 keys, bitonic
-    network up to 2048, radix sort beyond).  A fifth of the Gaussians are exact copies of
-    others, so equal depths must come out ordered by Gaussian index."""
+def dense_scene(n, copies):
+    """n large splats over a 48x48 view (9 tiles), so that every Gaussian lands in every
+    tile, plus `copies` exact copies of some of them (equal depths, which must come out
+    ordered by Gaussian index): every bucket holds n + copies keys."""
     base = inputs.make_scene(50 + n, n, 0, box=(-0.3, 0.3), log_scale=(0.5, 0.1),
                              t_scale_range=(0.5, 1.0), vel_std=0.0)
     rng = np.random.default_rng(n)
-    sc = base.subset(np.concatenate([np.arange(n), rng.choice(n, n // 5, replace=False)]))
-    cam = inputs.look_at((0.0, 0.0, -6.0), width=48, height=48)
+    sc = base.subset(np.concatenate([np.arange(n), rng.choice(n, copies, replace=False)]))
+    return sc, inputs.look_at((0.0, 0.0, -6.0), width=48, height=48)
+
+
+@pytest.mark.parametrize("n", [150, 300, 1200, 3000])
+def test_dense_tiles_every_sort_path(R, n):
+    """Buckets of ~1.2 n keys take each per-tile sort: chunks of 64 ranked and merged (up to
+    512 keys), radix sort beyond."""
+    sc, cam = dense_scene(n, n // 5)
+    check_frame(R, sc, cam, np.float32(0.5), bg=(0.1, 0.2, 0.3))
+
+
+@pytest.mark.parametrize("s", [1, 2, 63, 64, 65, 127, 128, 129, 192, 193, 255, 256, 257, 511, 512, 513])
+def test_sort_path_boundaries(R, s):
+    """Buckets of exactly s keys, at and around the limits of each sort path (ranking up
+    to 64 keys, 2, 4 and 8 merged chunks, radix sort beyond 512) and of a chunk (64)."""
+    copies = s // 5
+    sc, cam = dense_scene(s - copies, copies)
+    proj = oracle.project(sc, cam, 0.5)
+    assert int((proj["count"] > 0).sum()) == sc.n and bool((proj["count"] == 9).all())
     check_frame(R, sc, cam, np.float32(0.5), bg=(0.1, 0.2, 0.3))
 
 
