@@ -27,6 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# HIP binds each stream to one of the process's hardware queues (GPU_MAX_HW_QUEUES, 4 by
+# default).  With 4 queues the sweep's four streams, created after the one-stream kernel
+# pass's, measured 21.4 k frames/s; with 8, 27.2 k (as with 4 when four other streams had
+# been used first).  The benchmark allows 8 for its own process, before HIP initialises
+# (a larger value in the environment is kept); config.hip_hw_queues reports it.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+
 FRAMES_PER_STEP = 300
 # Blend roofline.  Algorithmic work per (pixel, splat) evaluation of Eq. 4, counted on
 # the definition: exponent -1/2(a dx^2 + c dy^2) - b dx dy (11 flops), exp (1),
@@ -174,26 +182,6 @@ def scene_order(render, ds_drawn):
     ds, _ = render.spatially_ordered(ds_drawn)
     torch.cuda.synchronize()
     return ds, 1000.0 * (time.perf_counter() - t0)
-
-
-def touch_streams(k):
-    """Run one tiny kernel on each of k new streams (kept alive to the end).
-
-    HIP binds a stream to one of the process's hardware queues (4 here) when the stream
-    is first used.  On the first streams a process uses, the four-stream sweep ran at
-    16.2-16.6 k frames/s (13.2 k with 2 hardware queues allowed, 10.9 k with 1: it
-    behaves as if those streams shared queues); on streams first used after three or
-    more others it ran at 20.9-21.5 k, as it does on its first streams when 8 hardware
-    queues are allowed.  Touching k streams first gives the sweep's streams the
-    placement of the fast case."""
-    import torch
-
-    global _TOUCHED
-    _TOUCHED = [torch.cuda.Stream() for _ in range(k)]
-    for st in _TOUCHED:
-        with torch.cuda.stream(st):
-            torch.zeros(16, device="cuda").add_(1.0)
-    torch.cuda.synchronize()
 
 
 def sweep(args, ds, cams, times, render, S, time_blends, tile_order, streams=None, cache=True):
@@ -587,7 +575,6 @@ def main():
     W, H = cams[0].width, cams[0].height
 
     frames = args.steps * args.frames
-    touch_streams(4)
     # the kernel pass: the sweep on one stream, every blend timed by HIP events attached to
     # its launch
     k_elapsed, blend_ms, _ = sweep(args, ds, cams, times, render, 1, True, True)
@@ -610,6 +597,7 @@ def main():
         "config": {"workload": "300k Gaussians (SH3, 32 clusters), 1352x1014, 20-camera arc x 300 times, "
                                "camera-stage cache on", "frames_per_step": args.frames, "streams": args.streams,
                    "camera_cache": "one, shared by the streams (camera stage once per camera)",
+                   "hip_hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                    "scene_order": "drawn order, reordered at load by d4dgs_spatial_order",
                    "tile_order": bool(args.tile_order),
                    "binning": "separate" if args.unfused else "fused",
