@@ -169,7 +169,7 @@ __device__ __forceinline__ void fold_raw(const float4 &p, const float4 &q, const
 // splat is plain (sigmoid opacities above 0.985 are rare).
 __device__ __forceinline__ bool splat_plain(const float4 &p, const float4 &q) {
     const float a = p.z, b = p.w, c = q.x;
-    return a > 0.0f && c > 0.0f && a * c - b * b > 1e-5f * (a * c) && q.y < 0.985f;
+    return (a > 0.0f) & (c > 0.0f) & (a * c - b * b > 1e-5f * (a * c)) & (q.y < 0.985f);
 }
 
 __device__ __forceinline__ void fold_splat(const float4 *__restrict__ rec, uint32_t gi, float4 &f0, float4 &f1,
@@ -190,8 +190,9 @@ __device__ __forceinline__ void fold_splat(const float4 *__restrict__ rec, uint3
 // with the bound inflated by 1% + 0.01 and by 1e-5 of the terms' magnitude -- far beyond
 // FP32 rounding, the approximate reciprocals and the exponent's own error (1e-4 in log2
 // units) -- so a splat that fails the test is skipped by every pixel of the box without
-// changing any decision.  A conic that is not positive definite with margin is never
-// skipped; amax clearly below 1/255 always is.
+// changing any decision (P1, P2 and the magnitude are formed with FMAs; the margin covers
+// either rounding).  A conic that is not positive definite with margin is never skipped;
+// amax clearly below 1/255 always is.
 __device__ __forceinline__ bool splat_reaches(const float4 &f0, const float4 &f1, float x0, float x1, float y0,
                                               float y1) {
     const float A = -f0.z, B = -0.5f * f0.w, C = -f1.x;
@@ -200,12 +201,15 @@ __device__ __forceinline__ bool splat_reaches(const float4 &f0, const float4 &f1
     const float Xn = __builtin_amdgcn_fmed3f(0.0f, X0, X1), Yn = __builtin_amdgcn_fmed3f(0.0f, Y0, Y1);
     const float ys = __builtin_amdgcn_fmed3f(-B * Xn * __builtin_amdgcn_rcpf(C), Y0, Y1);
     const float xs = __builtin_amdgcn_fmed3f(-B * Yn * __builtin_amdgcn_rcpf(A), X0, X1);
-    const float P1 = Xn * (A * Xn + 2.0f * B * ys) + C * ys * ys;
-    const float P2 = xs * (A * xs + 2.0f * B * Yn) + C * Yn * Yn;
-    const float mag = A * (Xn * Xn + xs * xs) + C * (ys * ys + Yn * Yn);
-    const bool pd = A > 0.0f && C > 0.0f && A * C - B * B > 1e-5f * (A * C);
-    if (thr < -0.02f) return false;  // amax clearly below 1/255: no point keeps it
-    return !pd || fminf(P1, P2) <= thr * 1.01f + 0.01f + 1e-5f * mag;
+    const float B2 = 2.0f * B;
+    const float P1 = __builtin_fmaf(Xn, __builtin_fmaf(A, Xn, B2 * ys), C * ys * ys);
+    const float P2 = __builtin_fmaf(xs, __builtin_fmaf(A, xs, B2 * Yn), C * Yn * Yn);
+    const float mag = __builtin_fmaf(A, __builtin_fmaf(Xn, Xn, xs * xs), C * __builtin_fmaf(ys, ys, Yn * Yn));
+    // the flags are combined without short-circuit branches (straight-line code); amax
+    // clearly below 1/255: no point keeps it
+    const bool pd = (A > 0.0f) & (C > 0.0f) & (A * C - B * B > 1e-5f * (A * C));
+    const bool near = fminf(P1, P2) <= __builtin_fmaf(thr, 1.01f, __builtin_fmaf(1e-5f, mag, 0.01f));
+    return !(thr < -0.02f) & (!pd | near);
 }
 
 // The exponent over one wavefront's pixel region, expanded about the region's centre
