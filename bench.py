@@ -60,6 +60,10 @@ PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_SUMMARY = os.path.join(PROFILES, "k_blend_pmc_traffic_300k_1352x1014.txt")
 BLEND_SOURCES = ("paper_2503_22159_amd/csrc/blend.hip", "paper_2503_22159_amd/csrc/internal.hpp",
                  "paper_2503_22159_amd/build.py")
+SWEEP_SUMMARY = os.path.join(PROFILES, "sweep_valu_pmc_300k_1352x1014.txt")
+SWEEP_SOURCES = ("paper_2503_22159_amd/csrc/project.hip", "paper_2503_22159_amd/csrc/emit.hpp",
+                 "paper_2503_22159_amd/csrc/binsort.hip", "paper_2503_22159_amd/csrc/blend.hip",
+                 "paper_2503_22159_amd/csrc/internal.hpp", "paper_2503_22159_amd/build.py")
 BWD_SUMMARY = os.path.join(PROFILES, "backward_pmc_300k_1352x1014.txt")
 BWD_SOURCES = ("paper_2503_22159_amd/csrc/backward.hip", "paper_2503_22159_amd/csrc/internal.hpp",
                "paper_2503_22159_amd/build.py")
@@ -516,6 +520,23 @@ def blend_roofline(mean_evals, blend_ms):
                          "source": os.path.relpath(TRAFFIC_SUMMARY, ROOT)}}
 
 
+def sweep_issue(frames_per_s):
+    """The whole frame against the chip's vector issue rate: the VALU wave instructions of
+    one sweep frame, all five kernels (committed SQ_INSTS_VALU summary over 1200 frames of
+    the 20-camera sweep; null once any of their sources change), times the measured frame
+    rate, as a share of what 1,024 SIMDs issue at one wave64 instruction per 4 cycles.
+    The four streams share the SIMDs, so a fraction near 1 means the sweep is bound by
+    vector issue, not by memory or latency."""
+    kv = counter_summary(SWEEP_SUMMARY, SWEEP_SOURCES)
+    insts = _num(kv, "valu_insts_per_frame")
+    ifr = None if insts is None else insts * frames_per_s * CYCLES_PER_VALU / (SIMDS * CLOCK_HZ)
+    return {"bound": "valu issue", "valu_insts_per_frame": insts,
+            "issue_floor_us_per_frame": None if insts is None else round(
+                insts * CYCLES_PER_VALU / SIMDS / CLOCK_HZ * 1e6, 2),
+            "issue_frac": None if ifr is None else round(ifr, 4),
+            "source": os.path.relpath(SWEEP_SUMMARY, ROOT)}
+
+
 def backward_rooflines(bw, bwd_ms, sh_degree):
     """Rooflines of the two adjoint kernels from the one-stream backward pass.
     k_blend_bwd (ALU): oracle-counted evaluations up to each pixel's last contributor x 46
@@ -640,6 +661,7 @@ def main():
         progress("CPU oracle done")
         out["cpu_baseline"] = base
         out["roofline"] = blend_roofline(mean_evals, blend_ms)
+        out["roofline"]["sweep"] = sweep_issue(out["value"])
         if bwd_ms is not None:
             out["roofline"]["backward"] = backward_rooflines(bw, bwd_ms, scene.sh_degree)
     print(json.dumps(out), flush=True)
