@@ -37,6 +37,7 @@ CamK make_camk(const d4dgs_camera &c) {
     k.H = c.height;
     k.TX = (c.width + kTile - 1) / kTile;
     k.TY = (c.height + kTile - 1) / kTile;
+    k.txm = div_magic((uint32_t)k.TX);
     return k;
 }
 

@@ -137,9 +137,8 @@ __global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(FLO
                                                            uint32_t capacity, const float2 *__restrict__ mdot,
                                                            const float *__restrict__ dLf) {
     constexpr int NR = FLOW ? 11 : 9;  // sums reduced per splat
-    int tile, unused;
-    if (!tile_unit(blockIdx.x, c.TX, c.TY, 1, order, tile, unused)) return;  // the same for the whole workgroup
-    const int tx = tile % c.TX, ty = tile / c.TX;
+    int tile, tx, ty, unused;
+    if (!tile_unit(blockIdx.x, c.TX, c.TY, c.txm, 1, order, tile, tx, ty, unused)) return;  // the same for the whole workgroup
     const int tid = threadIdx.x, w = tid / kWave, ln = lane_id();
     const size_t plane = (size_t)c.W * c.H;
     // this wavefront's 8x8 quadrant and this lane's pixel

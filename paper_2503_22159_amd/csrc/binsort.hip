@@ -606,11 +606,12 @@ __global__ __launch_bounds__(kWave) void k_tile_sort(const uint64_t *__restrict_
                                                     const uint32_t *__restrict__ ranges, int tiles,
                                                     uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                     const uint32_t *__restrict__ misc,
-                                                    const uint32_t *__restrict__ order, int TX, int TY) {
+                                                    const uint32_t *__restrict__ order, int TX, int TY,
+                                                    uint32_t txm) {
     if (misc[1] != 0u) return;
     __shared__ uint64_t sk[kMergeMax];
-    int tile, unused;
-    if (!tile_unit(blockIdx.x, TX, TY, 1, order, tile, unused)) return;
+    int tile, tx, ty, unused;
+    if (!tile_unit(blockIdx.x, TX, TY, txm, 1, order, tile, tx, ty, unused)) return;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     const uint32_t s = end - start;
     if (s == 0) return;
@@ -687,7 +688,7 @@ void launch_scatter_sort(const float4 *rec, const uint32_t *count, uint32_t *off
                            (const uint32_t *)ranges, tiles, order);
     hipLaunchKernelGGL(k_tile_sort, dim3(tile_grid(c.TX, c.TY, 1)), dim3(kWave), 0, st,
                        (const uint64_t *)ws.bucket, ws.alt, ranges, tiles, keys, vals, ws.misc,
-                       (const uint32_t *)order, c.TX, c.TY);
+                       (const uint32_t *)order, c.TX, c.TY, c.txm);
 }
 
 }  // namespace

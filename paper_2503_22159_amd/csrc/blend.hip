@@ -100,13 +100,15 @@ __global__ __launch_bounds__(4 * kWave) void k_blend(const float4 *__restrict__ 
     // only): arrays of one stride, so that one address register serves every read
     __shared__ float4 S0[WPT][kWave], S1[WPT][kWave], S2[WPT][kWave];
     __shared__ float2 S3[FLOW ? WPT : 1][FLOW ? kWave : 1];
-    int tile, unused;
-    if (!tile_unit(blockIdx.x, c.TX, c.TY, 1, order, tile, unused)) return;  // uniform over the workgroup
+    int tile, tx, ty, unused;
+    if (!tile_unit(blockIdx.x, c.TX, c.TY, c.txm, 1, order, tile, tx, ty, unused)) return;  // uniform per workgroup
     const int sub = threadIdx.x / kWave;
     float4 *s0 = S0[sub], *s1 = S1[sub], *s2 = S2[sub];
     float2 *s3 = S3[FLOW ? sub : 0];
-    const int tx = tile % c.TX, ty = tile / c.TX;
-    const int rx0 = tx * kTile + (sub % NXR) * RW, ry0 = ty * kTile + (sub / NXR) * RH;
+    // the wavefront's region, from the wave index in a scalar register (integer work on
+    // the scalar unit); the LDS arrays keep the vector form, which the loop addresses best
+    const int wsub = __builtin_amdgcn_readfirstlane(sub);
+    const int rx0 = tx * kTile + (wsub % NXR) * RW, ry0 = ty * kTile + (wsub / NXR) * RH;
     const int ln = lane_id();
     const int px = rx0 + ln % RW;
     // pixel-centre box of this wavefront (for skipping splats that cannot reach it) and
@@ -128,9 +130,10 @@ __global__ __launch_bounds__(4 * kWave) void k_blend(const float4 *__restrict__ 
         last[k] = 0u;
     }
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-    // software pipeline: list entries two batches ahead, records one batch ahead
-    float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
-    float2 nm = make_float2(0.f, 0.f);
+    // software pipeline: list entries two batches ahead, records one batch ahead (a lane
+    // reads its record registers only for list entries it has loaded)
+    float4 n0, n1, n2;
+    float2 nm;
     if (start + ln < end) {
         const uint32_t g = vals[start + ln];
         n0 = rec[3 * (size_t)g];

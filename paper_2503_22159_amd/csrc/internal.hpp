@@ -30,6 +30,7 @@ struct CamK {
     float fx, fy, cx, cy;
     float limx, limy, znear;
     int W, H, TX, TY;
+    uint32_t txm;  // div_magic(TX): tile rows and columns without a vector division
 };
 
 CamK make_camk(const d4dgs_camera &c);
@@ -258,22 +259,45 @@ __device__ __forceinline__ float sq_exponent(float K, float Lx, float Ly, float 
 // first) it starts with its long lists, so that they do not run alone at the end.
 __host__ __device__ inline int tile_grid(int TX, int TY, int upt) { return 8 * ((TY + 7) / 8) * TX * upt; }
 
+// Division by a divisor d > 0 known on the host: m = div_magic(d) = floor((2^32 - 1) / d)
+// gives n / d as mulhi(n, m) or one more (mulhi(n, m) > n / d - 1 for every 32-bit n), so
+// one correction makes it exact.  With n, d and m uniform over a wavefront the whole
+// division runs on the scalar unit (there is no scalar divide; the compiler's own
+// expansion of an integer division uses the vector unit's reciprocal).
+__host__ __device__ inline uint32_t div_magic(uint32_t d) { return 0xffffffffu / d; }
+
+__device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t d, uint32_t m, uint32_t &r) {
+    uint32_t q = __umulhi(n, m);
+    r = n - q * d;
+    if (r >= d) {
+        ++q;
+        r -= d;
+    }
+    return q;
+}
+
 __device__ __forceinline__ int class_rows(int TY, int x) { return TY > x ? (TY - 1 - x) / 8 + 1 : 0; }
 
-__device__ __forceinline__ bool tile_unit(int b, int TX, int TY, int upt, const uint32_t *__restrict__ order,
-                                          int &tile, int &sub) {
+// (tx, ty): the tile's column and row; txm = div_magic(TX).
+__device__ __forceinline__ bool tile_unit(int b, int TX, int TY, uint32_t txm, int upt,
+                                          const uint32_t *__restrict__ order, int &tile, int &tx, int &ty, int &sub) {
     const int x = b & 7, k = b >> 3;
     const int j = k / upt;  // the XCD's j-th tile
     sub = k - j * upt;
     if (j >= TX * class_rows(TY, x)) return false;
+    uint32_t r;
     if (order) {
         int off = 0;
         for (int y = 0; y < x; ++y) off += class_rows(TY, y);
         const uint32_t o = order[TX * off + j];
         if (o >= (uint32_t)(TX * TY)) return false;  // an order not written by the binning stays in bounds
         tile = (int)o;
+        ty = (int)udiv_magic(o, (uint32_t)TX, txm, r);
+        tx = (int)r;
     } else {
-        tile = (x + 8 * (j / TX)) * TX + j % TX;
+        ty = x + 8 * (int)udiv_magic((uint32_t)j, (uint32_t)TX, txm, r);
+        tx = (int)r;
+        tile = ty * TX + tx;
     }
     return true;
 }
