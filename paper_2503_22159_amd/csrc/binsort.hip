@@ -445,17 +445,31 @@ __device__ __forceinline__ void write_out(uint64_t k, uint32_t pos, uint32_t til
 // accesses before the ones that follow: a barrier of a one-wavefront workgroup.
 __device__ __forceinline__ void wave_step() { __syncthreads(); }
 
-// Number of keys of chunk c of sk (64 keys, sorted or not) below k: 32 broadcast reads of
-// two keys each.
-__device__ __forceinline__ uint32_t chunk_rank(const uint64_t *sk, int c, uint64_t k) {
+// Number of keys of chunk c of sk (64 keys, sorted or not) below k: np broadcast reads of
+// two keys each, np = ceil(len / 2) for a chunk holding len keys (the padding after them,
+// ~0, is never below a key).
+__device__ __forceinline__ uint32_t chunk_rank(const uint64_t *sk, int c, uint64_t k, uint32_t np) {
     const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(sk + c * kWave);
     uint32_t r = 0;
+    if (np == kWave / 2) {
 #pragma unroll 8
-    for (int j = 0; j < kWave / 2; ++j) {
-        const ulonglong2 kk = p[j];
-        r += (kk.x < k) + (kk.y < k);
+        for (int j = 0; j < kWave / 2; ++j) {
+            const ulonglong2 kk = p[j];
+            r += (kk.x < k) + (kk.y < k);
+        }
+    } else {  // the list's last chunk, partly filled
+#pragma unroll 4
+        for (uint32_t j = 0; j < np; ++j) {
+            const ulonglong2 kk = p[j];
+            r += (kk.x < k) + (kk.y < k);
+        }
     }
     return r;
+}
+
+// ceil(len / 2) for the len = min(64, s - 64 c) keys of chunk c of an s-key list
+__device__ __forceinline__ uint32_t chunk_pairs(uint32_t s, int c) {
+    return (min(s - (uint32_t)c * kWave, (uint32_t)kWave) + 1u) >> 1;
 }
 
 // Lower bound of k in chunk c of sk once it is sorted: the number of its keys below k (0..64),
@@ -500,8 +514,8 @@ __device__ __forceinline__ void wave_merge_sort(const uint64_t *__restrict__ buc
 #pragma unroll
     for (int c = 0; c < MAXC; c += 2) {
         if (c >= nch) break;
-        const uint32_t ra = chunk_rank(sk, c, k[c]);
-        const uint32_t rb = c + 1 < nch ? chunk_rank(sk, c + 1, k[c + 1]) : 0u;
+        const uint32_t ra = chunk_rank(sk, c, k[c], chunk_pairs(s, c));
+        const uint32_t rb = c + 1 < nch ? chunk_rank(sk, c + 1, k[c + 1], chunk_pairs(s, c + 1)) : 0u;
         if (k[c] != ~0ull) r[c] = ra;
         if (k[c + 1] != ~0ull) r[c + 1] = rb;
     }

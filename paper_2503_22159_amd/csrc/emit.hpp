@@ -27,6 +27,7 @@ struct EmitLds {
     uint32_t x0[kBlock], y0[kBlock], w[kBlock];
     uint32_t cell[kCells];  // per-tile counts (count pass) or ranks (scatter pass)
     uint32_t box[4][kBlock / kWave];
+    uint32_t mark[kBlock];  // emit_each: 1 + the lane whose instances start at a position
 };
 
 // The block's union rectangle of tiles (origin bx0, by0; uw x uh tiles) and whether its
@@ -97,24 +98,37 @@ __device__ __forceinline__ EmitBox emit_box(EmitLds &L, uint32_t cnt, uint32_t l
 }
 
 // Visits every instance of the block once: f(o, tile, cell) with o the owning thread of
-// the block.  A wave's instances are dealt to its lanes in turn (lane j takes instance
-// j, j + 64, ... of the wave's 64 Gaussians, the owner found by a binary search over the
-// wave prefix), so splats with large rectangles do not stall a wave.
+// the block.  A wave's instances are dealt to its lanes in rounds of 64 (lane l takes
+// instance r0 + l of the wave's 64 Gaussians' instances, in order), so splats with large
+// rectangles do not stall a wave.  An instance's owner is the last Gaussian (lane) whose
+// instances start at or before it: each Gaussian whose first instance falls in the round
+// marks that position with 1 + its lane, and an inclusive max-scan over the round's
+// positions, floored by the owner of the previous round's last instance, gives every
+// instance its owner.
 template <class F>
-__device__ __forceinline__ void emit_each(const EmitLds &L, const EmitBox &B, int TX, F f) {
-    const int wbase = (threadIdx.x / kWave) * kWave;
+__device__ __forceinline__ void emit_each(EmitLds &L, const EmitBox &B, int TX, F f) {
+    const int wbase = (threadIdx.x / kWave) * kWave, ln = lane_id();
     const uint32_t wtotal = L.incl[wbase + kWave - 1];
-    for (uint32_t j = lane_id(); j < wtotal; j += kWave) {
-        int lo = 0, hi = kWave - 1;  // owner: first lane whose inclusive prefix exceeds j
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (L.incl[wbase + mid] > j) hi = mid; else lo = mid + 1;
+    const uint32_t first = ln > 0 ? L.incl[wbase + ln - 1] : 0u;  // this lane's first instance
+    const bool has = L.incl[wbase + ln] > first;
+    uint32_t carry = 0u;  // 1 + the owner of the instance before the round (0: none yet)
+    for (uint32_t r0 = 0; r0 < wtotal; r0 += kWave) {
+        L.mark[wbase + ln] = 0u;
+        wave_lds_sync();
+        if (has && first >= r0 && first - r0 < (uint32_t)kWave) L.mark[wbase + (first - r0)] = (uint32_t)ln + 1u;
+        wave_lds_sync();
+        const uint32_t own = max(wave_incl_max(L.mark[wbase + ln]), carry);
+        carry = __builtin_amdgcn_readlane(own, kWave - 1);
+        const uint32_t j = r0 + ln;
+        if (j < wtotal) {
+            const int lo = (int)own - 1;
+            const int o = wbase + lo;
+            const uint32_t kk = j - (lo > 0 ? L.incl[o - 1] : 0u);
+            const uint32_t w = L.w[o];
+            const uint32_t tyy = L.y0[o] + kk / w, txx = L.x0[o] + kk % w;
+            f(o, tyy * (uint32_t)TX + txx, (tyy - B.by0) * B.uw + (txx - B.bx0));
         }
-        const int o = wbase + lo;
-        const uint32_t kk = j - (lo > 0 ? L.incl[o - 1] : 0u);
-        const uint32_t w = L.w[o];
-        const uint32_t tyy = L.y0[o] + kk / w, txx = L.x0[o] + kk % w;
-        f(o, tyy * (uint32_t)TX + txx, (tyy - B.by0) * B.uw + (txx - B.bx0));
+        wave_lds_sync();  // every lane has read its mark before the next round clears them
     }
 }
 

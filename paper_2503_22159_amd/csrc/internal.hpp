@@ -67,6 +67,27 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+// Inclusive max-scan over the wavefront, by the same moves (lanes shifted in from outside
+// a row give 0, the identity of an unsigned max).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+    v = max(v, dpp_u32<0x111>(v));
+    v = max(v, dpp_u32<0x112>(v));
+    v = max(v, dpp_u32<0x114>(v));
+    v = max(v, dpp_u32<0x118>(v));
+    v = max(v, dpp_u32<0x142, 0xa>(v));
+    v = max(v, dpp_u32<0x143, 0xc>(v));
+    return v;
+}
+
+// Orders a wavefront's LDS accesses before the ones after it.  The accesses of one
+// wavefront complete in order, so this costs no instruction; it keeps the compiler from
+// moving accesses across it.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The same on 64-bit values (both halves moved by DPP).
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
