@@ -136,6 +136,23 @@ def test_fused_full_size_frame(R):
         assert run_both(fused, sep, cams[j], np.float32(t))["num_inst"] > 0
 
 
+def test_huge_splats_match_oracle_binning(R):
+    """Splats covering up to the whole 640 x 480 image: a wavefront's 64 Gaussians own up
+    to 50k tile instances, which the count and scatter passes deal out in hundreds of
+    rounds of 64 (each instance's owner carried across rounds), with temporally culled
+    Gaussians (no instances) in between; every tile's list exceeds 512 keys (the radix
+    sort).  Lists, keys and ranges are compared with the oracle's binning."""
+    sc = inputs.make_scene(91, 4000, 1, clusters=8, cluster_box=(-3.0, 3.0), cluster_std=1.0, log_scale=(0.0, 0.8))
+    cam = inputs.arc_camera(4, width=640, height=480)
+    t = np.float32(0.45)
+    orc = oracle.bin(oracle.project(sc, cam, t, "f32"), cam)
+    assert orc["I"] > 2_000_000
+    ds, fused, sep = renderers(R, sc, cam.width, cam.height, capacity=orc["I"] + 1024)
+    a = run_both(fused, sep, cam, t)
+    assert a["status"] == 0 and a["num_inst"] == orc["I"]
+    assert_bins_equal(read_bins(fused.st), orc)
+
+
 def test_fused_large_image_scans_in_rounds(R):
     """2704 x 2028 has 21,463 tiles: the tile scan adds the counts up first, then scans
     in three rounds of 8,192."""
