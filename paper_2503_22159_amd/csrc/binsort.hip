@@ -488,8 +488,8 @@ __device__ __forceinline__ uint32_t chunk_lower_bound(const uint64_t *sk, int c,
 // ranked inside its chunk (the keys are unique: the rank is the number of the chunk's keys
 // below it) and every chunk is rewritten in sorted order in place; a key's position in the
 // tile's list is then its rank plus, for every other chunk, its lower bound there.  Per key
-// that is 64 comparisons and 7 (nch - 1) probes instead of the s comparisons of ranking
-// against the whole list.  Two chunks are ranked, and two keys searched, side by side, and
+// that is at most 64 comparisons (the last chunk's keys only, padding skipped) and
+// 7 (nch - 1) probes instead of the s comparisons of ranking against the whole list.  Two chunks are ranked, and two keys searched, side by side, and
 // each key's searches of the other chunks are interleaved, so that the dependent LDS reads
 // overlap.
 template <int MAXC>
