@@ -81,7 +81,7 @@ def _load(path):
     L.oc_version.restype = C.c_int
     for suf in ("f32", "f64"):
         f = getattr(L, "oc_project_" + suf)
-        f.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 14
+        f.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double] + [P] * 15
         f.restype = None
     L.oc_bin.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, P]
     L.oc_bin.restype = C.c_int64
@@ -241,12 +241,30 @@ def project(scene, cam, t, prec="f32", arrays=None):
     out["depth"] = np.zeros(n, np.float32)
     out["rect"] = np.zeros((4, n), np.int32)
     out["count"] = np.zeros(n, np.int32)
+    out["margin"] = np.zeros(n, dt)
     f = getattr(lib(), "oc_project_" + prec)
     f(C.byref(s), C.byref(c), float(t), *[_p(out[k]) for k in
-      ("p", "u", "covc", "m0", "md", "rgb", "m", "conic", "amax", "w", "depth", "rect", "count", "mdt")])
+      ("p", "u", "covc", "m0", "md", "rgb", "m", "conic", "amax", "w", "depth", "rect", "count", "mdt",
+       "margin")])
     del keep
     out["n"] = n
     return out
+
+
+NEAR_DECISION = 1e-5
+
+
+def near_decisions(scene, cam, t, rel=NEAR_DECISION):
+    """Gaussians whose time-stage integer decisions lie within `rel` (relative) of their
+    thresholds, evaluated in FP64: the temporal and near culls, the determinant's sign,
+    the guard-band clamps, the discriminant floor, the radius ceiling and the rectangle
+    floors (only the culls for a culled Gaussian).  Such a decision is one that FP32
+    arithmetic in another order could take the other way; when a projection parity test
+    fails, this count says whether the failure can be a rounding matter.  Returns
+    (count, indices)."""
+    m = project(scene, cam, t, "f64")["margin"]
+    idx = np.nonzero(m < rel)[0]
+    return int(idx.size), idx
 
 
 def bin(proj, cam):

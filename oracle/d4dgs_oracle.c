@@ -34,7 +34,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OC_VERSION 1
+#define OC_VERSION 2
 
 /* fp32(2 ln 255): tau^2 > KT * s_t^2  <=>  w < 1/255 (up to rounding) */
 #define OC_KT 11.0825272f
@@ -214,12 +214,13 @@ int oc_version(void) { return OC_VERSION; }
 /* ---------------- projection (camera stage + time stage) ----------------
  * Outputs are planar: p[3n], u[3n], covc[6n], m0[2n], md[2n], rgb[3n], m[2n],
  * conic[3n], amax[n], w[n], depth[n] (FP32 bits of the camera-space z at t),
- * rect[4n] (x0,y0,x1,y1), count[n], mdt[2n] (the 2D mean's velocity at t, the flow).
- * Any output pointer may be NULL.                                             */
+ * rect[4n] (x0,y0,x1,y1), count[n], mdt[2n] (the 2D mean's velocity at t, the flow),
+ * margin[n] (the smallest relative margin of the Gaussian's time-stage decisions, a
+ * diagnostic).  Any output pointer may be NULL.                                             */
 #define DEFINE_PROJECT(SUF, T)                                                                       \
     void oc_project_##SUF(const oc_scene *s, const oc_camera *cam, double t, T *p, T *u, T *covc,   \
                           T *m0, T *md, T *rgb, T *m, T *conic, T *amax, T *w, float *depth,         \
-                          int32_t *rect, int32_t *count, T *mdt)                                     \
+                          int32_t *rect, int32_t *count, T *mdt, T *margin)                          \
     {                                                                                                \
         int n = s->n, P = n_params(s->sh_degree);                                                    \
         _Pragma("omp parallel for schedule(static)") for (int g = 0; g < n; ++g)                     \
@@ -250,6 +251,7 @@ int oc_version(void) { return OC_VERSION; }
             for (int i = 0; i < 4; ++i)                                                              \
                 if (rect) rect[i * n + g] = r.count > 0 ? r.rect[i] : 0;                             \
             if (count) count[g] = r.count;                                                           \
+            if (margin) margin[g] = (T)r.margin;                                                     \
         }                                                                                            \
     }
 DEFINE_PROJECT(f32, float)

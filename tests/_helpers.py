@@ -28,11 +28,25 @@ def read_bins(st):
     return {"keys": keys, "values": vals, "ranges": ranges, "I": ni}
 
 
-def assert_projection_equal(gpu, orc, rgb_rtol=2e-6, amax_rtol=2e-6):
-    """Integer decisions and FP-contract quantities bit-exact; continuous values close."""
-    assert np.array_equal(gpu["count"], orc["count"]), np.nonzero(gpu["count"] != orc["count"])[0][:10]
+def assert_projection_equal(gpu, orc, rgb_rtol=2e-6, amax_rtol=2e-6, near=None):
+    """Integer decisions and FP-contract quantities bit-exact; continuous values close.
+    near (optional): (scene, cam, t) of the frame; on a mismatch of a decision the message
+    then gives the oracle's FP64 count of Gaussians within 1e-5 of a decision threshold
+    (oracle.near_decisions) and whether the mismatching ones are among them."""
+    def why(bad):
+        if near is None:
+            return bad[:10]
+        import oracle
+
+        n, idx = oracle.near_decisions(*near)
+        return bad[:10], f"{n} Gaussians within 1e-5 of a decision; mismatches among them: " \
+                         f"{np.isin(bad, idx).sum()} of {bad.size}"
+
+    bad = np.nonzero(gpu["count"] != orc["count"])[0]
+    assert bad.size == 0, why(bad)
     act = orc["count"] > 0
-    assert np.array_equal(gpu["rect"][:, act], orc["rect"][:, act])
+    bad = np.nonzero(np.any(gpu["rect"] != orc["rect"], axis=0) & act)[0]
+    assert bad.size == 0, why(bad)
     assert np.array_equal(gpu["depth"][act].view(np.uint32), orc["depth"][act].view(np.uint32))
     assert np.array_equal(gpu["m"][:, act].view(np.uint32), orc["m"][:, act].view(np.uint32))
     assert np.array_equal(gpu["conic"][:, act].view(np.uint32), orc["conic"][:, act].view(np.uint32))

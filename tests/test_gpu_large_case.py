@@ -104,7 +104,7 @@ def test_large_case_batch_forward_backward(R, scene):
         proj, bins, mb, res, dL = orc[i]
         keep, pix = ups[i]
         gp = decode_record(st, scene.n)
-        assert_projection_equal(gp, proj)
+        assert_projection_equal(gp, proj, near=(scene, cam, t))
         gb = read_bins(st)
         assert_bins_equal(gb, bins)
         # image on the sampled tiles only: off the sample the oracle's values are replaced

@@ -73,7 +73,7 @@ def test_times_frame_against_oracle(R):
     for i, t in enumerate(times):
         fr = tr.frames[i]
         orc_p = oracle.project(sc, cam, t, "f32")
-        assert_projection_equal(decode_record(fr, sc.n), orc_p)
+        assert_projection_equal(decode_record(fr, sc.n), orc_p, near=(sc, cam, t))
         ob = oracle.bin(orc_p, cam)
         assert_bins_equal(read_bins(fr), ob)
         res = oracle.blend(orc_p, ob, cam)
